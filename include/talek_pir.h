@@ -1,0 +1,267 @@
+/*
+ * talek_pir.h -- C ABI of the MI355X XOR-PIR server engine.
+ *
+ * One handle (pir_db) is one Talek server's PIR database: a blocked cuckoo
+ * table of n buckets, each bucket d slots of msg_bytes bytes (section "Server
+ * Design": buckets of equal size, each hash bucket is one PIR block). The
+ * engine answers batches of IT-PIR request vectors: for request row r,
+ *
+ *     resp[r] = XOR of every bucket j (0 <= j < n) whose request bit is 1,
+ *
+ * bit j of a row being bit (j & 7) of byte (j >> 3), least-significant first.
+ * This is the server step of the IT-PIR protocol (section "Background: PIR")
+ * and ProcessRead of the server interface (section "Problem Definition",
+ * Model). Bits past n in a row's last byte are ignored. Results are exact.
+ *
+ * Conventions for every call:
+ *   - Return value: PIR_OK (0) or a negative pir_status. No exception crosses
+ *     the ABI. On a validation error no output is touched.
+ *   - Host buffers belong to the caller; the library copies what it needs and
+ *     keeps no caller pointer after a call returns.
+ *   - Device buffers passed to *_async calls are read/written stream-ordered on
+ *     the given HIP stream; the caller keeps them alive until the stream has
+ *     passed the call.
+ *   - Calls on one handle are serialised internally (a mutex per handle).
+ *   - Epochs: writes are staged and become visible to reads issued after the
+ *     next pir_epoch_commit (the paper's periodic snapshot of the working copy
+ *     into the GPU, section "Evaluation", cost of operations). Reads always
+ *     answer from the last published snapshot.
+ *   - Device: a handle lives on the HIP device that was current at create.
+ *   - Any HIP runtime failure returns PIR_EDEVICE.
+ */
+#ifndef TALEK_PIR_H
+#define TALEK_PIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pir_db pir_db;
+typedef struct pir_cuckoo pir_cuckoo;
+
+enum pir_status {
+    PIR_OK = 0,
+    PIR_EINVAL = -1,  /* bad argument: NULL pointer, zero size, overflow, bad pitch */
+    PIR_ERANGE = -2,  /* bucket index >= n, or interest position >= m_bits */
+    PIR_ENOMEM = -3,  /* device or pinned host allocation failed */
+    PIR_EDEVICE = -4, /* a HIP runtime call failed */
+    PIR_EFULL = -5,   /* cuckoo insertion gave up after max_kicks evictions */
+    PIR_EBUSY = -6    /* admission refused: no memory slot free */
+};
+
+/* Text for a pir_status value (static storage; never NULL). */
+const char *pir_strerror(int code);
+
+/* Library version string, e.g. "talek-pir 0.1 gfx950". */
+const char *pir_version(void);
+
+/* ---------------------------------------------------------------- database */
+
+/*
+ * Create a database of n buckets x d slots x msg_bytes bytes on the current
+ * HIP device. The published snapshot starts all-zero (empty slots hold zero
+ * bytes). Fails with PIR_EINVAL when n, d or msg_bytes is 0 or n*d*msg_bytes
+ * overflows, PIR_ENOMEM when device memory runs out. *out is set only on
+ * success. (Section "Writing into a Cuckoo Hash Table": b buckets of d
+ * messages of size z.)
+ */
+int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out);
+
+/* Free every device and host resource of the handle. NULL is a no-op. Waits
+ * for the handle's outstanding work first. */
+void pir_db_destroy(pir_db *db);
+
+/* Geometry: n, d, msg_bytes and the bucket size d * msg_bytes. Any output
+ * pointer may be NULL. */
+int pir_db_shape(const pir_db *db, uint64_t *n, uint32_t *d, uint32_t *msg_bytes,
+                 uint64_t *bucket_bytes);
+
+/*
+ * Stage the d * msg_bytes bytes of one bucket (ProcessWrite's effect on the
+ * table, applied to the next snapshot). A later write to the same bucket in
+ * the same epoch wins. PIR_ERANGE if bucket >= n; PIR_EINVAL on NULL data.
+ */
+int pir_db_write_bucket(pir_db *db, uint64_t bucket, const uint8_t *data);
+
+/* Stage count consecutive buckets starting at first: count * d * msg_bytes
+ * bytes, row-major. PIR_ERANGE if first + count > n. */
+int pir_db_write_range(pir_db *db, uint64_t first, uint64_t count, const uint8_t *data);
+
+/*
+ * Publish every staged bucket write and the open epoch's interest bits: reads
+ * issued after this call (on any stream) answer from the new snapshot, reads
+ * issued before it finish on the old one. Double-buffered on the device: the
+ * staged buckets are written into the back copy, the copies swap, and the
+ * same buckets are then replayed into the new back copy once the reads that
+ * still use it have finished. Returns the new epoch number in *epoch_out
+ * (may be NULL).
+ */
+int pir_epoch_commit(pir_db *db, uint64_t *epoch_out);
+
+/* Number of epochs published so far. */
+uint64_t pir_epoch(const pir_db *db);
+
+/* ------------------------------------------------------------------- reads */
+
+/*
+ * Answer B request vectors (ProcessRead, section "Problem Definition";
+ * server step 5 of section "Background: PIR").
+ *   req_bits: B rows of ceil(n / 8) bytes, row-major, host memory.
+ *   resp:     B rows of d * msg_bytes bytes, row-major, host memory, written.
+ * Blocks until the answers are in resp. B = 0 is a no-op returning PIR_OK.
+ * NULL req_bits or resp with B > 0 -> PIR_EINVAL.
+ */
+int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp);
+
+/*
+ * Same answer, device memory, asynchronous on a HIP stream (hipStream_t,
+ * NULL = the default stream).
+ *   d_req:  B rows, row r at d_req + r * req_pitch; req_pitch >= ceil(n / 8).
+ *   d_resp: B rows, row r at d_resp + r * resp_pitch; resp_pitch >= d * msg_bytes.
+ * Any pitch and alignment is accepted; rows that are not 4-byte (requests) or
+ * 16-byte (responses) aligned are restaged through library scratch on the same
+ * stream. Returns once the work is enqueued.
+ */
+int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B,
+                         void *d_resp, uint64_t resp_pitch, void *hip_stream);
+
+/*
+ * Uneven batch stream: n_batches batches, batch k holding sizes[k] request
+ * rows. Batch k reads request rows req_first[k] .. req_first[k] + sizes[k] - 1
+ * of d_req and writes response rows resp_first[k] .. of d_resp (row indices,
+ * host arrays; a NULL array means the batches' rows are concatenated in
+ * order). Every batch is answered exactly as pir_read_batch_async would
+ * answer it. The work items of all batches (request tile x bucket split x
+ * column group) go through one persistent work-queue kernel launch per chunk
+ * of batches (a chunk is bounded by the split-partial scratch it needs),
+ * claimed in batch order, so one batch's tail overlaps the next batch's head;
+ * the launch sequence is captured in a HIP graph and replayed when the same
+ * stream shape, buffers and snapshot repeat. Requires 4-byte aligned request
+ * rows with req_pitch % 4 == 0 and ceil(n/8) % 4 == 0, and 16-byte aligned
+ * response rows with resp_pitch % 16 == 0 and d * msg_bytes % 16 == 0
+ * (PIR_EINVAL otherwise). (Section "Evaluation": read requests are batched
+ * and forwarded to the GPU; the leader may reorder reads.)
+ */
+int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req_pitch,
+                          const uint32_t *sizes, const uint64_t *req_first, uint32_t n_batches,
+                          void *d_resp, uint64_t resp_pitch, const uint64_t *resp_first,
+                          void *hip_stream);
+
+/* --------------------------------------------------------- kernel schedule */
+
+/* Kernel families of the read path. */
+enum pir_kernel_kind {
+    PIR_KERNEL_AUTO = 0,   /* tuning table, else the built-in heuristic */
+    PIR_KERNEL_MASK = 1,   /* branch-free masked XOR (one 3-input op per word) */
+    PIR_KERNEL_SKIP = 2,   /* wave-uniform zero-skip of unselected buckets */
+    PIR_KERNEL_M4R = 3     /* Four-Russians: XOR-combination tables in LDS */
+};
+
+/* A read schedule: kernel family, requests per wave tile, bucket splits
+ * (0 = heuristic), unroll depth (0 = default). */
+typedef struct pir_plan {
+    int32_t kind;
+    uint32_t tile;
+    uint32_t splits;
+    uint32_t unroll;
+} pir_plan;
+
+/* Force a schedule for subsequent reads of this handle (kind AUTO restores
+ * the automatic choice). PIR_EINVAL for an unsupported combination. */
+int pir_set_plan(pir_db *db, const pir_plan *plan);
+
+/* The schedule the next read of B rows would use. */
+int pir_get_plan(pir_db *db, uint32_t B, pir_plan *plan);
+
+/*
+ * Autotune: time every candidate schedule for batches of B rows on the
+ * handle's current snapshot (iters timed launches each, after one warm-up)
+ * and record the fastest in the tuning table under (n, B class, bucket
+ * bytes). best (may be NULL) receives the winner, best_us its mean time.
+ */
+int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *best_us);
+
+/* Save / load the tuning table as JSON. Loading merges into the table. */
+int pir_tune_save(const char *path);
+int pir_tune_load(const char *path);
+
+/* ------------------------------------------------- private notifications */
+
+/*
+ * Configure the global interest vector (section "Private Notifications"):
+ * m_bits Bloom-filter bits, union over the deltas of the last window_epochs
+ * published epochs. Resets the vector. Defaults: 2^20 bits, 8 epochs.
+ * PIR_EINVAL for m_bits == 0, m_bits > 2^32 or window_epochs == 0.
+ */
+int pir_interest_config(pir_db *db, uint64_t m_bits, uint32_t window_epochs);
+
+/*
+ * OR one write's interest-vector bits into the open epoch's delta: k bit
+ * positions, each < m_bits (PIR_ERANGE otherwise, nothing applied). They
+ * become visible at the next pir_epoch_commit.
+ */
+int pir_interest_add(pir_db *db, const uint32_t *pos, uint32_t k);
+
+/*
+ * ProcessGetUpdates: copy the published global interest vector (the OR of
+ * the window's deltas) into out, ceil(m_bits / 8) bytes, bit p at byte p >> 3,
+ * bit p & 7. PIR_EINVAL if out_bytes is smaller.
+ */
+int pir_interest_vector(pir_db *db, uint8_t *out, uint64_t out_bytes);
+
+/* Device-memory variant of pir_interest_vector, stream-ordered. */
+int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void *hip_stream);
+
+/* ------------------------------------------------- server cuckoo table */
+
+/*
+ * The server's DRAM working copy: a blocked cuckoo table bound to db (same
+ * n, d, msg_bytes), applying Write requests as section "Writing into a Cuckoo
+ * Hash Table" describes: delete the oldest message when `capacity` messages
+ * are live (0 = never), store in beta1 or else beta2 if either has a free slot
+ * (beta1 first, lowest free slot), otherwise walk evictions driven by one
+ * SplitMix64 stream seeded with s_cuckoo (one draw & 1 picks beta_e at the
+ * first both-full step; each eviction draws once, victim slot = draw % d),
+ * giving up after max_kicks evictions. The item in hand at that point is
+ * dropped and the call returns PIR_EFULL with its id in *dropped_id.
+ * Every bucket the call changes is marked dirty; pir_cuckoo_stage copies the
+ * dirty buckets into db's staged writes.
+ */
+int pir_cuckoo_create(pir_db *db, uint64_t capacity, uint64_t s_cuckoo, uint32_t max_kicks,
+                      pir_cuckoo **out);
+/* A table with no database bound (host only, no GPU needed): the same rules,
+ * pir_cuckoo_stage returns PIR_EINVAL. For replicas that only keep the
+ * working copy, and for checking the placement logic on its own. */
+int pir_cuckoo_create_detached(uint64_t n, uint32_t d, uint32_t msg_bytes, uint64_t capacity,
+                               uint64_t s_cuckoo, uint32_t max_kicks, pir_cuckoo **out);
+void pir_cuckoo_destroy(pir_cuckoo *c);
+
+/* One Write: ids are the caller's message ids; payload is msg_bytes bytes. */
+int pir_cuckoo_insert(pir_cuckoo *c, uint64_t id, uint64_t beta1, uint64_t beta2,
+                      const uint8_t *payload, uint64_t *dropped_id);
+
+/* count Writes in order; status[i] / dropped[i] (either may be NULL) receive
+ * each insert's result. Returns PIR_OK, or the first hard error (EINVAL /
+ * ERANGE); EFULL results are reported per item only. */
+int pir_cuckoo_insert_many(pir_cuckoo *c, uint64_t count, const uint64_t *ids,
+                           const uint64_t *beta1, const uint64_t *beta2,
+                           const uint8_t *payloads, int32_t *status, uint64_t *dropped);
+
+/* Stage every dirty bucket into the bound database (visible after the next
+ * pir_epoch_commit). *staged receives the number of buckets (may be NULL). */
+int pir_cuckoo_stage(pir_cuckoo *c, uint64_t *staged);
+
+/* Host working copy, for inspection: n * d * msg_bytes bytes; per-slot message
+ * ids (0 = empty) and occupancy (n * d entries each; either may be NULL). */
+int pir_cuckoo_table(const pir_cuckoo *c, uint8_t *out, uint64_t out_bytes);
+int pir_cuckoo_slots(const pir_cuckoo *c, uint64_t *ids, uint8_t *occupied);
+uint64_t pir_cuckoo_live(const pir_cuckoo *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TALEK_PIR_H */

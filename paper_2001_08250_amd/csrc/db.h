@@ -1,0 +1,106 @@
+// Internal definition of the pir_db handle, shared by the host-side sources.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/talek_pir.h"
+#include "engine.h"
+
+namespace talek {
+
+// Device scratch owned per HIP stream, so concurrent reads on different
+// streams never share partial or restaging buffers.
+struct Scratch {
+    void *req = nullptr;
+    uint64_t req_cap = 0;
+    void *resp = nullptr;
+    uint64_t resp_cap = 0;
+    void *part = nullptr;
+    uint64_t part_cap = 0;
+    void *aux = nullptr;      // persistent-queue tables and counters
+    uint64_t aux_cap = 0;
+    hipGraphExec_t exec = nullptr;  // captured stream read
+    std::vector<uint64_t> sig;      // what the captured graph bakes in
+};
+
+int hip_status(hipError_t e);  // hipSuccess -> PIR_OK, else PIR_EDEVICE
+
+// Grow a device buffer to at least `bytes` (contents are not kept).
+int ensure_device(void **p, uint64_t *cap, uint64_t bytes);
+
+void destroy_stream_graph(Scratch &sc);
+
+}  // namespace talek
+
+struct pir_db {
+    std::recursive_mutex mu;
+    int device = 0;
+    int num_cus = 256;
+    uint64_t n = 0;
+    uint32_t d = 0, z = 0;
+    uint64_t bucket_bytes = 0;  // d * z
+    uint64_t stride = 0;        // bucket_bytes rounded up to 16
+    uint64_t qbytes = 0;        // ceil(n / 8)
+    uint64_t qpitch = 0;        // internal request pitch (multiple of 16)
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;  // graph capture only, never executes
+
+    // double-buffered snapshot: buf[front] is published, buf[front ^ 1] is
+    // the back copy that receives staged writes
+    uint8_t *buf[2] = {nullptr, nullptr};
+    int front = 0;
+    bool have_back = false;
+    uint64_t epoch = 0;
+    hipEvent_t published = nullptr;  // end of the last commit's device work
+    // events recorded after async reads, per buffer and per stream
+    std::map<hipStream_t, hipEvent_t> readers[2];
+
+    // staged bucket writes (pinned host rows, `stride` bytes each)
+    uint8_t *stage_host = nullptr;
+    uint64_t *stage_idx_host = nullptr;
+    uint64_t stage_cap = 0;   // rows
+    uint64_t stage_rows = 0;
+    std::unordered_map<uint64_t, uint64_t> stage_slot;
+    void *stage_dev = nullptr;
+    uint64_t stage_dev_cap = 0;
+    void *stage_idx_dev = nullptr;
+    uint64_t stage_idx_dev_cap = 0;
+    // buckets changed in the open epoch
+    std::vector<uint8_t> dirty_mark;
+    std::vector<uint64_t> dirty;
+    bool all_dirty = false;
+
+    std::unordered_map<hipStream_t, talek::Scratch> scratch;
+    talek::Plan forced{0, 0, 0, 0};
+
+    // interest vector
+    uint64_t m_bits = 0;
+    uint64_t iv_words = 0;
+    uint32_t window = 0;
+    uint32_t *iv_ring = nullptr;       // window x iv_words
+    uint32_t *iv_global[2] = {nullptr, nullptr};
+    std::vector<uint32_t> pos_pending;
+    void *pos_dev = nullptr;
+    uint64_t pos_dev_cap = 0;
+    uint32_t *pos_host = nullptr;      // pinned
+    uint64_t pos_host_cap = 0;
+};
+
+namespace talek {
+// Schedule for a read of B rows on db (forced plan, tuning table, heuristic).
+Plan choose_plan(pir_db *db, uint32_t B);
+// Geometry of a read of B rows of the published snapshot.
+ReadGeom read_geom(pir_db *db, const void *q, uint64_t qpitch, uint32_t B, void *out, uint64_t out_pitch);
+// Scratch of a stream (created on first use).
+Scratch &scratch_for(pir_db *db, hipStream_t s);
+// Record that stream s reads buffer b (commits wait for it before reusing b).
+int note_reader(pir_db *db, int b, hipStream_t s);
+// Tuning table lookup: true and *p if an entry exists for (n, B class, stride).
+bool tune_lookup(uint64_t n, uint32_t B, uint64_t stride, Plan *p);
+}  // namespace talek

@@ -1,0 +1,102 @@
+// Internal interface between the host library and the device kernels.
+// Nothing here is part of the C ABI (include/talek_pir.h).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace talek {
+
+// Kernel families (values match enum pir_kernel_kind).
+enum Kind : int { KIND_AUTO = 0, KIND_MASK = 1, KIND_SKIP = 2, KIND_M4R = 3 };
+
+// Geometry of one read launch. D rows are `stride` bytes apart (stride is
+// bucket_bytes rounded up to 16; padding bytes are zero). Request rows are
+// `qpitch` bytes apart, qpitch % 4 == 0, each row readable up to
+// round_up(ceil(n/8), 4) bytes. Output rows are `out_pitch` bytes apart,
+// out_pitch % 16 == 0, and receive `stride` bytes each.
+struct ReadGeom {
+    const void *D;
+    uint64_t n;
+    uint64_t stride;
+    const void *Q;
+    uint64_t qpitch;
+    uint32_t B;
+    void *out;
+    uint64_t out_pitch;
+};
+
+struct Plan {
+    int kind;
+    uint32_t tile;     // requests per wave
+    uint32_t splits;   // bucket-range splits (1 = none)
+    uint32_t unroll;   // buckets loaded ahead
+};
+
+// Device scratch the read needs for split partials: bytes.
+uint64_t partial_bytes(const ReadGeom &g, const Plan &p);
+
+// Fill in a complete plan (tile, splits, unroll) for geometry g from a
+// partial request (kind may be AUTO; zero fields mean "choose").
+Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus);
+
+// Is the (kind, tile, unroll) combination compiled in?
+bool plan_supported(const Plan &p);
+
+// Enqueue the read: kernels on `stream`; `partials` must hold
+// partial_bytes(g, p) bytes when p.splits > 1.
+hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+
+// --- epoch writes ------------------------------------------------------
+// dst[idx[e]] = src[e] for e < count; each entry `stride` bytes, 16-aligned.
+hipError_t launch_scatter_rows(void *dst, const void *src, const uint64_t *idx, uint64_t count,
+                               uint64_t stride, hipStream_t stream);
+// dst[idx[e]] = src[idx[e]] for e < count.
+hipError_t launch_copy_rows(void *dst, const void *src, const uint64_t *idx, uint64_t count,
+                            uint64_t stride, hipStream_t stream);
+
+// --- interest vector -----------------------------------------------------
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);           // bytes % 4 == 0
+hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count, hipStream_t stream);
+hipError_t launch_or_rows(uint32_t *out, const uint32_t *rows, uint32_t nrows, uint64_t words,
+                          hipStream_t stream);
+
+// --- persistent work-queue read (uneven batch streams) ------------------
+struct QueueItem {       // one work item: 16 bytes
+    uint32_t batch;      // index into the batch table
+    uint32_t rt;         // request tile within the batch
+    uint32_t s;          // bucket split
+    uint32_t cg;         // column group (1 KiB x 4 waves)
+};
+struct QueueBatch {      // per batch: 64 bytes (same layout on host and device)
+    uint64_t q_off;      // byte offset of the batch's first request row
+    uint64_t out_off;    // byte offset of the batch's first response row
+    uint64_t part_off;   // byte offset of the batch's partial buffer
+    uint32_t B;
+    uint32_t splits;
+    uint32_t words_per_split;
+    uint32_t n_rt;
+    uint32_t n_cg;
+    uint32_t group_base; // first completion counter of this batch
+    uint32_t pad[4];
+};
+struct QueueGeom {
+    const void *D;
+    uint64_t n;
+    uint64_t stride;
+    const void *Q;       // base of all batches' request rows
+    uint64_t qpitch;
+    void *out;           // base of all batches' response rows
+    uint64_t out_pitch;
+    void *partials;      // base of all batches' partial buffers
+    const QueueItem *items;
+    const QueueBatch *batches;
+    uint32_t *head;      // work counter, zero before launch
+    uint32_t *done;      // completion counters, zero before launch
+    uint32_t n_items;
+};
+constexpr uint32_t QUEUE_TILE = 16;   // requests per wave in the queue kernel
+hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream);
+uint32_t queue_grid(int num_cus);
+
+}  // namespace talek

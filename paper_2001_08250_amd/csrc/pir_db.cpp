@@ -1,0 +1,624 @@
+// C ABI of the XOR-PIR engine: database handle, epoch-published writes,
+// reads, and the global interest vector.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "db.h"
+
+using namespace talek;
+
+namespace talek {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PIR_OK : PIR_EDEVICE; }
+
+int ensure_device(void **p, uint64_t *cap, uint64_t bytes)
+{
+    if (bytes <= *cap && *p)
+        return PIR_OK;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+        if (e != hipSuccess)
+            return PIR_EDEVICE;
+    }
+    uint64_t want = std::max<uint64_t>(bytes, 256);
+    if (hipMalloc(p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return PIR_ENOMEM;
+    }
+    *cap = want;
+    return PIR_OK;
+}
+
+Scratch &scratch_for(pir_db *db, hipStream_t s) { return db->scratch[s]; }
+
+void destroy_stream_graph(Scratch &sc)
+{
+    if (sc.exec)
+        hipGraphExecDestroy(sc.exec);
+    sc.exec = nullptr;
+    sc.sig.clear();
+}
+
+int note_reader(pir_db *db, int b, hipStream_t s)
+{
+    auto it = db->readers[b].find(s);
+    hipEvent_t ev;
+    if (it == db->readers[b].end()) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return PIR_EDEVICE;
+        db->readers[b].emplace(s, ev);
+    } else {
+        ev = it->second;
+    }
+    return hipEventRecord(ev, s) == hipSuccess ? PIR_OK : PIR_EDEVICE;
+}
+
+ReadGeom read_geom(pir_db *db, const void *q, uint64_t qpitch, uint32_t B, void *out, uint64_t out_pitch)
+{
+    ReadGeom g{};
+    g.D = db->buf[db->front];
+    g.n = db->n;
+    g.stride = db->stride;
+    g.Q = q;
+    g.qpitch = qpitch;
+    g.B = B;
+    g.out = out;
+    g.out_pitch = out_pitch;
+    return g;
+}
+
+Plan choose_plan(pir_db *db, uint32_t B)
+{
+    ReadGeom g = read_geom(db, nullptr, db->qpitch, B, nullptr, db->stride);
+    Plan want = db->forced;
+    if (want.kind == KIND_AUTO) {
+        Plan tuned;
+        if (tune_lookup(db->n, B, db->stride, &tuned))
+            want = tuned;
+    }
+    return resolve_plan(g, want, db->num_cus);
+}
+
+}  // namespace talek
+
+namespace {
+
+constexpr uint64_t STAGE_BYTES = 64ull << 20;  // pinned staging for bucket writes
+
+#define HIP_TRY(x)                                                                                                 \
+    do {                                                                                                           \
+        hipError_t e_ = (x);                                                                                       \
+        if (e_ != hipSuccess)                                                                                      \
+            return PIR_EDEVICE;                                                                                    \
+    } while (0)
+
+#define PIR_TRY(x)                                                                                                 \
+    do {                                                                                                           \
+        int r_ = (x);                                                                                              \
+        if (r_ != PIR_OK)                                                                                          \
+            return r_;                                                                                             \
+    } while (0)
+
+int ensure_back(pir_db *db)
+{
+    if (db->have_back)
+        return PIR_OK;
+    const uint64_t bytes = db->n * db->stride;
+    if (!db->buf[db->front ^ 1]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return PIR_ENOMEM;
+        }
+        db->buf[db->front ^ 1] = static_cast<uint8_t *>(p);
+    }
+    HIP_TRY(hipMemcpyAsync(db->buf[db->front ^ 1], db->buf[db->front], bytes, hipMemcpyDeviceToDevice, db->stream));
+    db->have_back = true;
+    return PIR_OK;
+}
+
+void mark_dirty(pir_db *db, uint64_t b)
+{
+    if (db->all_dirty || db->dirty_mark[b])
+        return;
+    db->dirty_mark[b] = 1;
+    db->dirty.push_back(b);
+}
+
+// Apply the staged rows to the back copy; afterwards the staging is empty.
+int flush_stage(pir_db *db)
+{
+    if (db->stage_rows == 0)
+        return PIR_OK;
+    PIR_TRY(ensure_back(db));
+    const uint64_t rows = db->stage_rows;
+    PIR_TRY(ensure_device(&db->stage_dev, &db->stage_dev_cap, rows * db->stride));
+    PIR_TRY(ensure_device(&db->stage_idx_dev, &db->stage_idx_dev_cap, rows * sizeof(uint64_t)));
+    HIP_TRY(hipMemcpyAsync(db->stage_dev, db->stage_host, rows * db->stride, hipMemcpyHostToDevice, db->stream));
+    HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->stage_idx_host, rows * sizeof(uint64_t), hipMemcpyHostToDevice,
+                           db->stream));
+    HIP_TRY(launch_scatter_rows(db->buf[db->front ^ 1], db->stage_dev, static_cast<uint64_t *>(db->stage_idx_dev),
+                                rows, db->stride, db->stream));
+    HIP_TRY(hipStreamSynchronize(db->stream));  // staging rows are reused next
+    for (uint64_t i = 0; i < rows; ++i)
+        mark_dirty(db, db->stage_idx_host[i]);
+    db->stage_rows = 0;
+    db->stage_slot.clear();
+    return PIR_OK;
+}
+
+int stage_row(pir_db *db, uint64_t bucket, const uint8_t *data)
+{
+    auto it = db->stage_slot.find(bucket);
+    uint64_t slot;
+    if (it != db->stage_slot.end()) {
+        slot = it->second;
+    } else {
+        if (db->stage_rows == db->stage_cap)
+            PIR_TRY(flush_stage(db));
+        slot = db->stage_rows++;
+        db->stage_slot.emplace(bucket, slot);
+        db->stage_idx_host[slot] = bucket;
+    }
+    uint8_t *row = db->stage_host + slot * db->stride;
+    memcpy(row, data, db->bucket_bytes);
+    if (db->stride > db->bucket_bytes)
+        memset(row + db->bucket_bytes, 0, db->stride - db->bucket_bytes);
+    return PIR_OK;
+}
+
+// Make `s` wait until every reader of buffer `b` recorded so far is done.
+int wait_readers(pir_db *db, int b, hipStream_t s)
+{
+    for (auto &kv : db->readers[b])
+        HIP_TRY(hipStreamWaitEvent(s, kv.second, 0));
+    return PIR_OK;
+}
+
+int interest_alloc(pir_db *db, uint64_t m_bits, uint32_t window)
+{
+    hipFree(db->iv_ring);
+    hipFree(db->iv_global[0]);
+    hipFree(db->iv_global[1]);
+    db->iv_ring = db->iv_global[0] = db->iv_global[1] = nullptr;
+    const uint64_t words = (m_bits + 31) / 32;
+    void *p = nullptr;
+    if (hipMalloc(&p, words * 4 * window) != hipSuccess)
+        return PIR_ENOMEM;
+    db->iv_ring = static_cast<uint32_t *>(p);
+    for (int i = 0; i < 2; ++i) {
+        if (hipMalloc(&p, words * 4) != hipSuccess)
+            return PIR_ENOMEM;
+        db->iv_global[i] = static_cast<uint32_t *>(p);
+    }
+    db->m_bits = m_bits;
+    db->iv_words = words;
+    db->window = window;
+    db->pos_pending.clear();
+    HIP_TRY(launch_fill_zero(db->iv_ring, words * 4 * window, db->stream));
+    HIP_TRY(launch_fill_zero(db->iv_global[0], words * 4, db->stream));
+    HIP_TRY(launch_fill_zero(db->iv_global[1], words * 4, db->stream));
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    return PIR_OK;
+}
+
+void free_db(pir_db *db)
+{
+    if (db->stream)
+        (void)hipStreamSynchronize(db->stream);
+    for (auto &kv : db->scratch) {
+        destroy_stream_graph(kv.second);
+        hipFree(kv.second.req);
+        hipFree(kv.second.resp);
+        hipFree(kv.second.part);
+        hipFree(kv.second.aux);
+    }
+    for (int b = 0; b < 2; ++b) {
+        for (auto &kv : db->readers[b])
+            hipEventDestroy(kv.second);
+        hipFree(db->buf[b]);
+        hipFree(db->iv_global[b]);
+    }
+    hipFree(db->iv_ring);
+    hipFree(db->stage_dev);
+    hipFree(db->stage_idx_dev);
+    hipFree(db->pos_dev);
+    if (db->stage_host)
+        hipHostFree(db->stage_host);
+    if (db->stage_idx_host)
+        hipHostFree(db->stage_idx_host);
+    if (db->pos_host)
+        hipHostFree(db->pos_host);
+    if (db->published)
+        hipEventDestroy(db->published);
+    if (db->stream)
+        hipStreamDestroy(db->stream);
+    if (db->capture_stream)
+        hipStreamDestroy(db->capture_stream);
+    delete db;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pir_strerror(int code)
+{
+    switch (code) {
+    case PIR_OK: return "ok";
+    case PIR_EINVAL: return "invalid argument";
+    case PIR_ERANGE: return "index out of range";
+    case PIR_ENOMEM: return "out of memory";
+    case PIR_EDEVICE: return "HIP device error";
+    case PIR_EFULL: return "cuckoo insertion failed (eviction bound reached)";
+    case PIR_EBUSY: return "no memory slot free (admission refused)";
+    default: return "unknown error";
+    }
+}
+
+const char *pir_version(void) { return "talek-pir 0.1 gfx950"; }
+
+int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
+{
+    if (!out || n == 0 || d == 0 || msg_bytes == 0)
+        return PIR_EINVAL;
+    const uint64_t bucket = (uint64_t)d * msg_bytes;
+    if (bucket > (1ull << 30) || n > (1ull << 40))
+        return PIR_EINVAL;
+    const uint64_t stride = (bucket + 15) & ~15ull;
+    if (stride / 16 > 0xffffffffull || n > UINT64_MAX / stride)
+        return PIR_EINVAL;
+    pir_db *db = new (std::nothrow) pir_db();
+    if (!db)
+        return PIR_ENOMEM;
+    db->n = n;
+    db->d = d;
+    db->z = msg_bytes;
+    db->bucket_bytes = bucket;
+    db->stride = stride;
+    db->qbytes = (n + 7) / 8;
+    db->qpitch = (db->qbytes + 15) & ~15ull;
+    int rc = PIR_OK;
+    do {
+        if (hipGetDevice(&db->device) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, db->device) == hipSuccess && prop.multiProcessorCount > 0)
+            db->num_cus = prop.multiProcessorCount;
+        if (hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        if (hipStreamCreateWithFlags(&db->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+            rc = PIR_EDEVICE;
+            break;
+        }
+        if (hipEventCreateWithFlags(&db->published, hipEventDisableTiming) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        void *p = nullptr;
+        if (hipMalloc(&p, n * stride) != hipSuccess) { rc = PIR_ENOMEM; break; }
+        db->buf[0] = static_cast<uint8_t *>(p);
+        if (launch_fill_zero(db->buf[0], n * stride, db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        db->stage_cap = std::max<uint64_t>(1, std::min<uint64_t>(n, STAGE_BYTES / stride));
+        if (hipHostMalloc(&p, db->stage_cap * stride, hipHostMallocDefault) != hipSuccess) { rc = PIR_ENOMEM; break; }
+        db->stage_host = static_cast<uint8_t *>(p);
+        if (hipHostMalloc(&p, db->stage_cap * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+            rc = PIR_ENOMEM;
+            break;
+        }
+        db->stage_idx_host = static_cast<uint64_t *>(p);
+        db->dirty_mark.assign(n, 0);
+        if ((rc = interest_alloc(db, 1ull << 20, 8)) != PIR_OK)
+            break;
+        if (hipEventRecord(db->published, db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        if (hipStreamSynchronize(db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
+    } while (0);
+    if (rc != PIR_OK) {
+        (void)hipGetLastError();
+        free_db(db);
+        return rc;
+    }
+    *out = db;
+    return PIR_OK;
+}
+
+void pir_db_destroy(pir_db *db)
+{
+    if (!db)
+        return;
+    hipSetDevice(db->device);
+    free_db(db);
+}
+
+int pir_db_shape(const pir_db *db, uint64_t *n, uint32_t *d, uint32_t *msg_bytes, uint64_t *bucket_bytes)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (n) *n = db->n;
+    if (d) *d = db->d;
+    if (msg_bytes) *msg_bytes = db->z;
+    if (bucket_bytes) *bucket_bytes = db->bucket_bytes;
+    return PIR_OK;
+}
+
+int pir_db_write_bucket(pir_db *db, uint64_t bucket, const uint8_t *data)
+{
+    if (!db || !data)
+        return PIR_EINVAL;
+    if (bucket >= db->n)
+        return PIR_ERANGE;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    return stage_row(db, bucket, data);
+}
+
+int pir_db_write_range(pir_db *db, uint64_t first, uint64_t count, const uint8_t *data)
+{
+    if (!db || (count && !data))
+        return PIR_EINVAL;
+    if (first > db->n || count > db->n - first)
+        return PIR_ERANGE;
+    if (count == 0)
+        return PIR_OK;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    if (count < db->stage_cap / 2) {
+        for (uint64_t i = 0; i < count; ++i)
+            PIR_TRY(stage_row(db, first + i, data + i * db->bucket_bytes));
+        return PIR_OK;
+    }
+    // Large range: keep write order (staged rows first), then copy straight
+    // into the back copy.
+    PIR_TRY(flush_stage(db));
+    PIR_TRY(ensure_back(db));
+    uint8_t *dst = db->buf[db->front ^ 1] + first * db->stride;
+    HIP_TRY(hipMemcpy2DAsync(dst, db->stride, data, db->bucket_bytes, db->bucket_bytes, count,
+                             hipMemcpyHostToDevice, db->stream));
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    if (count == db->n) {
+        db->all_dirty = true;
+    } else {
+        for (uint64_t i = 0; i < count; ++i)
+            mark_dirty(db, first + i);
+    }
+    return PIR_OK;
+}
+
+int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
+{
+    if (!db)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    PIR_TRY(flush_stage(db));
+    const bool changed = db->all_dirty || !db->dirty.empty();
+    const int back = db->front ^ 1;
+
+    // interest vector: the open epoch's delta replaces the oldest ring slot;
+    // the new global vector (OR of the window) goes with the back copy.
+    if (db->pos_pending.size() > db->pos_host_cap) {
+        if (db->pos_host)
+            hipHostFree(db->pos_host);
+        db->pos_host = nullptr;
+        db->pos_host_cap = 0;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, db->pos_pending.size() * 4, hipHostMallocDefault) != hipSuccess)
+            return PIR_ENOMEM;
+        db->pos_host = static_cast<uint32_t *>(p);
+        db->pos_host_cap = db->pos_pending.size();
+    }
+    const uint64_t npos = db->pos_pending.size();
+    if (npos) {
+        memcpy(db->pos_host, db->pos_pending.data(), npos * 4);
+        PIR_TRY(ensure_device(&db->pos_dev, &db->pos_dev_cap, npos * 4));
+        HIP_TRY(hipMemcpyAsync(db->pos_dev, db->pos_host, npos * 4, hipMemcpyHostToDevice, db->stream));
+    }
+    // The back copy's vector may still be read by async readers of the
+    // buffer it belonged to before the last swap.
+    PIR_TRY(wait_readers(db, back, db->stream));
+    uint32_t *slot = db->iv_ring + (db->epoch % db->window) * db->iv_words;
+    HIP_TRY(launch_fill_zero(slot, db->iv_words * 4, db->stream));
+    HIP_TRY(launch_set_bits(slot, static_cast<uint32_t *>(db->pos_dev), npos, db->stream));
+    HIP_TRY(launch_or_rows(db->iv_global[back], db->iv_ring, db->window, db->iv_words, db->stream));
+    db->pos_pending.clear();
+
+    if (changed) {
+        PIR_TRY(ensure_back(db));
+    } else if (!db->have_back) {
+        // nothing written: only the interest vector moves. Keep the
+        // snapshot where it is and copy the new vector into the front slot.
+        PIR_TRY(wait_readers(db, db->front, db->stream));
+        HIP_TRY(hipMemcpyAsync(db->iv_global[db->front], db->iv_global[back], db->iv_words * 4,
+                               hipMemcpyDeviceToDevice, db->stream));
+        HIP_TRY(hipEventRecord(db->published, db->stream));
+        HIP_TRY(hipStreamSynchronize(db->stream));
+        db->epoch++;
+        if (epoch_out)
+            *epoch_out = db->epoch;
+        return PIR_OK;
+    }
+    // publish: swap the copies
+    HIP_TRY(hipEventRecord(db->published, db->stream));
+    const int old_front = db->front;
+    db->front = back;
+    // replay this epoch's buckets into the new back copy once its readers
+    // are done
+    PIR_TRY(wait_readers(db, old_front, db->stream));
+    if (db->all_dirty || db->dirty.size() * 2 > db->n) {
+        HIP_TRY(hipMemcpyAsync(db->buf[old_front], db->buf[db->front], db->n * db->stride, hipMemcpyDeviceToDevice,
+                               db->stream));
+    } else if (!db->dirty.empty()) {
+        const uint64_t cnt = db->dirty.size();
+        PIR_TRY(ensure_device(&db->stage_idx_dev, &db->stage_idx_dev_cap, cnt * sizeof(uint64_t)));
+        HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->dirty.data(), cnt * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               db->stream));
+        HIP_TRY(launch_copy_rows(db->buf[old_front], db->buf[db->front],
+                                 static_cast<uint64_t *>(db->stage_idx_dev), cnt, db->stride, db->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    for (uint64_t b : db->dirty)
+        db->dirty_mark[b] = 0;
+    db->dirty.clear();
+    db->all_dirty = false;
+    db->epoch++;
+    if (epoch_out)
+        *epoch_out = db->epoch;
+    return PIR_OK;
+}
+
+uint64_t pir_epoch(const pir_db *db) { return db ? db->epoch : 0; }
+
+int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!req_bits || !resp)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    Scratch &sc = scratch_for(db, db->stream);
+    PIR_TRY(ensure_device(&sc.req, &sc.req_cap, (uint64_t)B * db->qpitch));
+    PIR_TRY(ensure_device(&sc.resp, &sc.resp_cap, (uint64_t)B * db->stride));
+    HIP_TRY(hipMemcpy2DAsync(sc.req, db->qpitch, req_bits, db->qbytes, db->qbytes, B, hipMemcpyHostToDevice,
+                             db->stream));
+    ReadGeom g = read_geom(db, sc.req, db->qpitch, B, sc.resp, db->stride);
+    Plan p = choose_plan(db, B);
+    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
+    HIP_TRY(launch_read(g, p, sc.part, db->stream));
+    HIP_TRY(hipMemcpy2DAsync(resp, db->bucket_bytes, sc.resp, db->stride, db->bucket_bytes, B,
+                             hipMemcpyDeviceToHost, db->stream));
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    return PIR_OK;
+}
+
+int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B, void *d_resp,
+                         uint64_t resp_pitch, void *hip_stream)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!d_req || !d_resp || req_pitch < db->qbytes || resp_pitch < db->bucket_bytes)
+        return PIR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    HIP_TRY(hipStreamWaitEvent(s, db->published, 0));
+    Scratch &sc = scratch_for(db, s);
+    const void *q = d_req;
+    uint64_t qp = req_pitch;
+    // The kernel reads whole 32-bit request words: rows must be 4-byte
+    // aligned and the last word of every row must lie inside it.
+    if ((reinterpret_cast<uintptr_t>(d_req) & 3) || (req_pitch & 3) || (db->qbytes & 3)) {
+        PIR_TRY(ensure_device(&sc.req, &sc.req_cap, (uint64_t)B * db->qpitch));
+        HIP_TRY(hipMemcpy2DAsync(sc.req, db->qpitch, d_req, req_pitch, db->qbytes, B, hipMemcpyDeviceToDevice, s));
+        q = sc.req;
+        qp = db->qpitch;
+    }
+    const bool direct = !(reinterpret_cast<uintptr_t>(d_resp) & 15) && !(resp_pitch & 15) &&
+                        db->stride == db->bucket_bytes;
+    void *out = d_resp;
+    uint64_t op = resp_pitch;
+    if (!direct) {
+        PIR_TRY(ensure_device(&sc.resp, &sc.resp_cap, (uint64_t)B * db->stride));
+        out = sc.resp;
+        op = db->stride;
+    }
+    ReadGeom g = read_geom(db, q, qp, B, out, op);
+    Plan p = choose_plan(db, B);
+    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
+    HIP_TRY(launch_read(g, p, sc.part, s));
+    if (!direct)
+        HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,
+                                 hipMemcpyDeviceToDevice, s));
+    return note_reader(db, db->front, s);
+}
+
+int pir_set_plan(pir_db *db, const pir_plan *plan)
+{
+    if (!db || !plan)
+        return PIR_EINVAL;
+    Plan p{plan->kind, plan->tile, plan->splits, plan->unroll};
+    if (p.kind < KIND_AUTO || p.kind > KIND_M4R)
+        return PIR_EINVAL;
+    if (p.kind != KIND_AUTO) {
+        ReadGeom g = read_geom(db, nullptr, db->qpitch, std::max<uint32_t>(p.tile, 1), nullptr, db->stride);
+        Plan full = resolve_plan(g, p, db->num_cus);
+        if (!plan_supported(full))
+            return PIR_EINVAL;
+    }
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    db->forced = p;
+    return PIR_OK;
+}
+
+int pir_get_plan(pir_db *db, uint32_t B, pir_plan *plan)
+{
+    if (!db || !plan)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    Plan p = choose_plan(db, std::max<uint32_t>(B, 1));
+    plan->kind = p.kind;
+    plan->tile = p.tile;
+    plan->splits = p.splits;
+    plan->unroll = p.unroll;
+    return PIR_OK;
+}
+
+int pir_interest_config(pir_db *db, uint64_t m_bits, uint32_t window_epochs)
+{
+    if (!db || m_bits == 0 || m_bits > (1ull << 32) || window_epochs == 0 || window_epochs > 4096)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    for (int b = 0; b < 2; ++b)
+        for (auto &kv : db->readers[b])
+            HIP_TRY(hipEventSynchronize(kv.second));
+    return interest_alloc(db, m_bits, window_epochs);
+}
+
+int pir_interest_add(pir_db *db, const uint32_t *pos, uint32_t k)
+{
+    if (!db || (k && !pos))
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    for (uint32_t i = 0; i < k; ++i)
+        if (pos[i] >= db->m_bits)
+            return PIR_ERANGE;
+    db->pos_pending.insert(db->pos_pending.end(), pos, pos + k);
+    return PIR_OK;
+}
+
+int pir_interest_vector(pir_db *db, uint8_t *out, uint64_t out_bytes)
+{
+    if (!db || !out)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    const uint64_t bytes = (db->m_bits + 7) / 8;
+    if (out_bytes < bytes)
+        return PIR_EINVAL;
+    HIP_TRY(hipSetDevice(db->device));
+    HIP_TRY(hipMemcpyAsync(out, db->iv_global[db->front], bytes, hipMemcpyDeviceToHost, db->stream));
+    HIP_TRY(hipStreamSynchronize(db->stream));
+    return PIR_OK;
+}
+
+int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void *hip_stream)
+{
+    if (!db || !d_out)
+        return PIR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    const uint64_t bytes = (db->m_bits + 7) / 8;
+    if (out_bytes < bytes)
+        return PIR_EINVAL;
+    HIP_TRY(hipSetDevice(db->device));
+    HIP_TRY(hipStreamWaitEvent(s, db->published, 0));
+    HIP_TRY(hipMemcpyAsync(d_out, db->iv_global[db->front], bytes, hipMemcpyDeviceToDevice, s));
+    return note_reader(db, db->front, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Read-schedule selection: kernel family, request tile, bucket splits, unroll.
+#include <algorithm>
+
+#include "engine.h"
+
+namespace talek {
+
+bool tile_plan_supported(const Plan &p);
+hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+bool m4r_plan_supported(const Plan &p);
+hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+uint32_t m4r_tasks(const ReadGeom &g, const Plan &p);
+
+namespace {
+
+constexpr uint64_t PARTIAL_CAP = 256ull << 20;  // bytes of split partials per read
+
+uint32_t pow2_at_least(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+bool plan_supported(const Plan &p)
+{
+    if (p.kind == KIND_M4R)
+        return m4r_plan_supported(p);
+    return tile_plan_supported(p);
+}
+
+uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
+{
+    if (p.splits <= 1)
+        return 0;
+    return (uint64_t)p.splits * g.B * g.stride;
+}
+
+Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
+{
+    Plan p = want;
+    if (p.kind == KIND_AUTO)
+        p.kind = KIND_MASK;
+    const uint64_t nwords = (g.n + 31) / 32;
+    const uint32_t stride16 = (uint32_t)(g.stride / 16);
+    uint64_t units;  // independent workgroup tasks per split
+    if (p.kind == KIND_M4R) {
+        if (p.tile == 0)
+            p.tile = g.B <= 128 ? 32 : 64;
+        if (p.unroll == 0)
+            p.unroll = 8;
+        units = m4r_tasks(g, Plan{p.kind, p.tile, 1, p.unroll});
+    } else {
+        if (p.tile == 0)
+            p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;
+        if (p.unroll == 0)
+            p.unroll = p.tile <= 2 ? 16 : 8;
+        const uint64_t n_rt = (g.B + p.tile - 1) / p.tile;
+        const uint64_t n_cg = (stride16 + 255) / 256;
+        units = n_rt * n_cg;
+    }
+    if (p.splits == 0) {
+        const uint64_t target = (uint64_t)std::max(num_cus, 1) * 8;
+        uint64_t s = (target + units - 1) / std::max<uint64_t>(units, 1);
+        s = std::min<uint64_t>(s, std::max<uint64_t>(nwords / 2, 1));  // >= 64 buckets per split
+        const uint64_t per_split = (uint64_t)g.B * g.stride;
+        if (per_split)
+            s = std::min<uint64_t>(s, std::max<uint64_t>(PARTIAL_CAP / per_split, 1));
+        p.splits = (uint32_t)std::max<uint64_t>(s, 1);
+    }
+    p.splits = (uint32_t)std::min<uint64_t>(p.splits, std::max<uint64_t>(nwords, 1));
+    return p;
+}
+
+hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+{
+    if (g.B == 0)
+        return hipSuccess;
+    if (p.kind == KIND_M4R)
+        return launch_m4r_read(g, p, partials, stream);
+    return launch_tile_read(g, p, partials, stream);
+}
+
+}  // namespace talek

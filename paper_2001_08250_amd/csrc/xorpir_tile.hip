@@ -1,0 +1,370 @@
+// XOR-PIR read kernels for gfx950: tiled masked / zero-skip families and the
+// split-partial reduction.
+//
+// The server answer (section "Background: PIR", server step) is the GF(2)
+// product of the request bit matrix R (B x n) with the database D (n buckets
+// of `stride` bytes): resp[r] = XOR over j with R[r][j] = 1 of D[j].
+//
+// Mapping on CDNA4 (wave64):
+//  * A workgroup is 4 waves. Each lane owns 16 bytes of a bucket row, so one
+//    wave covers a 1 KiB column chunk and a workgroup a 4 KiB column group.
+//    Loads of D are 16 B per lane, fully coalesced (global_load_dwordx4).
+//  * A wave accumulates T requests ("tile") in VGPRs: acc[T] x 4 dwords.
+//  * Request bits are wave-uniform (every lane of the wave works on the same
+//    bucket), so the 32-bit request words are fetched with scalar loads and
+//    every per-(request, bucket) decision lives on the SALU.
+//  * MASK family: acc ^= data & mask, one v_bitop3_b32 per dword (truth table
+//    0x78 = S0 ^ (S1 & S2)) with the 0 / ~0 mask built on the SALU.
+//  * SKIP family: a wave-uniform branch skips unselected buckets, so only
+//    selected buckets cost a v_xor (half of them for uniform requests).
+//  * Buckets are split into `splits` contiguous ranges (multiples of 32
+//    buckets); each split writes a partial answer and a second pass XORs the
+//    partials (XOR is associative and commutative, so this is exact).
+//  * Work decomposition is XCD-aware: workgroups are dispatched round-robin
+//    over the 8 XCDs, so task t is given to blockIdx (t % per) * 8 + t / per
+//    with request tiles fastest. The request tiles that share a (split,
+//    column group) slice of D then run together on one XCD and reuse it from
+//    that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "engine.h"
+
+namespace talek {
+namespace {
+
+constexpr int WG = 256;
+constexpr uint32_t COLS_PER_WG = 4 * 64;  // uint4 columns per workgroup (4 KiB)
+
+struct TileArgs {
+    const uint4 *D;
+    uint64_t n;
+    uint32_t stride16;
+    uint32_t B;
+    const uint32_t *Q;
+    uint64_t qpitch_w;
+    uint4 *out;
+    uint64_t out_row16;
+    uint64_t out_split16;
+    uint32_t n_rt, n_cg, splits, words_per_split, tasks_per_xcd;
+};
+
+__device__ __forceinline__ uint32_t xor_and(uint32_t acc, uint32_t v, uint32_t m)
+{
+    return __builtin_amdgcn_bitop3_b32(acc, v, m, 0x78);  // acc ^ (v & m)
+}
+
+template <int T, int KIND>
+__device__ __forceinline__ void apply_bucket(uint4 (&acc)[T], const uint4 v, const uint32_t (&qw)[T],
+                                             const int bit)
+{
+#pragma unroll
+    for (int r = 0; r < T; ++r) {
+        if constexpr (KIND == KIND_MASK) {
+            const uint32_t m = 0u - ((qw[r] >> bit) & 1u);
+            acc[r].x = xor_and(acc[r].x, v.x, m);
+            acc[r].y = xor_and(acc[r].y, v.y, m);
+            acc[r].z = xor_and(acc[r].z, v.z, m);
+            acc[r].w = xor_and(acc[r].w, v.w, m);
+        } else {
+            if ((qw[r] >> bit) & 1u) {
+                acc[r].x ^= v.x;
+                acc[r].y ^= v.y;
+                acc[r].z ^= v.z;
+                acc[r].w ^= v.w;
+            }
+        }
+    }
+}
+
+// Accumulate buckets [jb, je) (jb a multiple of 32) of column `colc` for the
+// T request rows starting at r0 into acc. Rows >= B contribute nothing.
+template <int T, int KIND, int U>
+__device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__restrict__ D, uint32_t stride16,
+                                                uint64_t n, const uint32_t *__restrict__ Q, uint64_t qpitch_w,
+                                                uint32_t B, uint32_t r0, uint32_t colc, uint64_t jb, uint64_t je)
+{
+    static_assert(32 % U == 0, "unroll must divide 32");
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+        acc[r] = make_uint4(0u, 0u, 0u, 0u);
+    if (jb >= je)
+        return;
+    const uint4 *Dc = D + colc;
+    const uint64_t last = je - 1;
+    uint4 nxt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        nxt[u] = Dc[std::min<uint64_t>(jb + u, last) * stride16];
+
+    uint32_t qw[T];
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+        qw[r] = 0u;
+    for (uint64_t j = jb; j < je; j += U) {
+        if ((j & 31u) == 0) {
+            const uint64_t w = j >> 5;
+            uint32_t valid = ~0u;
+            if (((w + 1) << 5) > n)
+                valid = (1u << (n & 31u)) - 1u;
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+                qw[r] = (r0 + r < B) ? (Q[(uint64_t)(r0 + r) * qpitch_w + w] & valid) : 0u;
+        }
+        uint4 cur[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            cur[u] = nxt[u];
+        if (j + U < je) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                nxt[u] = Dc[std::min<uint64_t>(j + U + u, last) * stride16];
+        }
+        const int b0 = (int)(j & 31u);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            apply_bucket<T, KIND>(acc, cur[u], qw, b0 + u);
+    }
+}
+
+template <int T, int KIND, int U>
+__global__ __launch_bounds__(WG) void xorpir_tile_kernel(const TileArgs a)
+{
+    const uint32_t L = blockIdx.x;
+    const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
+    if (t >= a.n_rt * a.n_cg * a.splits)
+        return;
+    const uint32_t rt = t % a.n_rt;
+    const uint32_t rest = t / a.n_rt;
+    const uint32_t cg = rest % a.n_cg;
+    const uint32_t s = rest / a.n_cg;
+
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave_col = cg * COLS_PER_WG + wave * 64u;
+    if (wave_col >= a.stride16)
+        return;  // this wave's column chunk is past the row end
+    const uint32_t col = wave_col + lane;
+    const bool col_ok = col < a.stride16;
+    const uint32_t colc = col_ok ? col : wave_col;
+
+    const uint32_t r0 = rt * T;
+    const uint64_t nwords = (a.n + 31) >> 5;
+    const uint64_t wb = (uint64_t)s * a.words_per_split;
+    const uint64_t we = std::min<uint64_t>(nwords, wb + a.words_per_split);
+    const uint64_t jb = wb << 5;
+    const uint64_t je = std::min<uint64_t>(a.n, we << 5);
+
+    uint4 acc[T];
+    tile_accumulate<T, KIND, U>(acc, a.D, a.stride16, a.n, a.Q, a.qpitch_w, a.B, r0, colc, jb, je);
+
+    if (col_ok) {
+        uint4 *o = a.out + (uint64_t)s * a.out_split16 + col;
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+            if (r0 + r < a.B)
+                o[(uint64_t)(r0 + r) * a.out_row16] = acc[r];
+    }
+}
+
+// Persistent work-queue read over a stream of uneven batches. Workgroups
+// claim items with one atomic counter until the queue is empty (no waiting
+// on other workgroups, so every workgroup exits). Items are ordered batch by
+// batch. When a batch is split over bucket ranges, each split stores its
+// partial answer, publishes it (release fence + completion counter) and the
+// workgroup that completes a (batch, request tile, column group) last XORs
+// the partials into the response rows (acquire fence first).
+template <int KIND>
+__global__ __launch_bounds__(WG) void xorpir_queue_kernel(const QueueGeom g)
+{
+    constexpr int T = QUEUE_TILE;
+    constexpr int U = 8;
+    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_last;
+    const uint32_t stride16 = (uint32_t)(g.stride / 16);
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t nwords = (g.n + 31) >> 5;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(g.head, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= g.n_items)
+            break;
+        const QueueItem item = g.items[it];
+        const QueueBatch bt = g.batches[item.batch];
+        const uint32_t wave_col = item.cg * COLS_PER_WG + wave * 64u;
+        const bool wave_ok = wave_col < stride16;
+        const uint32_t col = wave_col + lane;
+        const bool col_ok = wave_ok && col < stride16;
+        const uint32_t colc = col_ok ? col : (wave_ok ? wave_col : 0u);
+        const uint32_t r0 = item.rt * T;
+        const uint64_t wb = (uint64_t)item.s * bt.words_per_split;
+        const uint64_t we = std::min<uint64_t>(nwords, wb + bt.words_per_split);
+        const uint64_t jb = wb << 5;
+        const uint64_t je = std::min<uint64_t>(g.n, we << 5);
+        const uint32_t *Q = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.Q) + bt.q_off);
+        uint4 acc[T];
+        if (wave_ok)
+            tile_accumulate<T, KIND, U>(acc, static_cast<const uint4 *>(g.D), stride16, g.n, Q, g.qpitch / 4,
+                                        bt.B, r0, colc, jb, je);
+        uint4 *out = reinterpret_cast<uint4 *>(static_cast<uint8_t *>(g.out) + bt.out_off);
+        const uint64_t out_row16 = g.out_pitch / 16;
+        if (bt.splits <= 1) {
+            if (col_ok) {
+#pragma unroll
+                for (int r = 0; r < T; ++r)
+                    if (r0 + r < bt.B)
+                        out[(uint64_t)(r0 + r) * out_row16 + col] = acc[r];
+            }
+            continue;
+        }
+        uint4 *part = reinterpret_cast<uint4 *>(static_cast<uint8_t *>(g.partials) + bt.part_off);
+        const uint64_t split16 = (uint64_t)bt.B * stride16;
+        if (col_ok) {
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+                if (r0 + r < bt.B)
+                    part[(uint64_t)item.s * split16 + (uint64_t)(r0 + r) * stride16 + col] = acc[r];
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t grp = bt.group_base + item.rt * bt.n_cg + item.cg;
+            s_last = (atomicAdd(g.done + grp, 1u) == bt.splits - 1) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if (col_ok) {
+                for (uint32_t r = r0; r < std::min<uint32_t>(r0 + T, bt.B); ++r) {
+                    uint4 x = make_uint4(0u, 0u, 0u, 0u);
+                    for (uint32_t s = 0; s < bt.splits; ++s) {
+                        const uint4 v = part[(uint64_t)s * split16 + (uint64_t)r * stride16 + col];
+                        x.x ^= v.x;
+                        x.y ^= v.y;
+                        x.z ^= v.z;
+                        x.w ^= v.w;
+                    }
+                    out[(uint64_t)r * out_row16 + col] = x;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// resp[r][c] = XOR over s of partials[s][r][c]
+__global__ __launch_bounds__(WG) void xor_splits_kernel(const uint4 *__restrict__ P, uint64_t split16,
+                                                        uint32_t splits, uint64_t count, uint32_t stride16,
+                                                        uint4 *__restrict__ out, uint64_t out_row16)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= count)
+        return;
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t s = 0; s < splits; ++s) {
+        const uint4 v = P[(uint64_t)s * split16 + i];
+        acc.x ^= v.x;
+        acc.y ^= v.y;
+        acc.z ^= v.z;
+        acc.w ^= v.w;
+    }
+    const uint64_t r = i / stride16, c = i % stride16;
+    out[r * out_row16 + c] = acc;
+}
+
+using TileFn = void (*)(const TileArgs);
+
+template <int KIND, int U>
+TileFn pick_tile(uint32_t T)
+{
+    switch (T) {
+    case 1: return xorpir_tile_kernel<1, KIND, U>;
+    case 2: return xorpir_tile_kernel<2, KIND, U>;
+    case 4: return xorpir_tile_kernel<4, KIND, U>;
+    case 8: return xorpir_tile_kernel<8, KIND, U>;
+    case 16: return xorpir_tile_kernel<16, KIND, U>;
+    case 24: return xorpir_tile_kernel<24, KIND, U>;
+    case 32: return xorpir_tile_kernel<32, KIND, U>;
+    default: return nullptr;
+    }
+}
+
+template <int KIND>
+TileFn pick_tile_u(uint32_t T, uint32_t U)
+{
+    switch (U) {
+    case 4: return pick_tile<KIND, 4>(T);
+    case 8: return pick_tile<KIND, 8>(T);
+    case 16: return pick_tile<KIND, 16>(T);
+    default: return nullptr;
+    }
+}
+
+TileFn tile_fn(const Plan &p)
+{
+    if (p.kind == KIND_MASK)
+        return pick_tile_u<KIND_MASK>(p.tile, p.unroll);
+    if (p.kind == KIND_SKIP)
+        return pick_tile_u<KIND_SKIP>(p.tile, p.unroll);
+    return nullptr;
+}
+
+}  // namespace
+
+uint32_t queue_grid(int num_cus) { return (uint32_t)std::max(num_cus, 1) * 4; }
+
+hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(xorpir_queue_kernel<KIND_MASK>, dim3(grid), dim3(WG), 0, stream, g);
+    return hipGetLastError();
+}
+
+bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
+
+hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+{
+    TileFn fn = tile_fn(p);
+    if (!fn)
+        return hipErrorInvalidValue;
+    TileArgs a{};
+    a.D = static_cast<const uint4 *>(g.D);
+    a.n = g.n;
+    a.stride16 = (uint32_t)(g.stride / 16);
+    a.B = g.B;
+    a.Q = static_cast<const uint32_t *>(g.Q);
+    a.qpitch_w = g.qpitch / 4;
+    a.n_rt = (g.B + p.tile - 1) / p.tile;
+    a.n_cg = (a.stride16 + COLS_PER_WG - 1) / COLS_PER_WG;
+    a.splits = p.splits;
+    const uint64_t nwords = (g.n + 31) / 32;
+    a.words_per_split = (uint32_t)((nwords + p.splits - 1) / p.splits);
+    if (p.splits > 1) {
+        a.out = static_cast<uint4 *>(partials);
+        a.out_row16 = a.stride16;
+        a.out_split16 = (uint64_t)g.B * a.stride16;
+    } else {
+        a.out = static_cast<uint4 *>(g.out);
+        a.out_row16 = g.out_pitch / 16;
+        a.out_split16 = 0;
+    }
+    const uint64_t tasks = (uint64_t)a.n_rt * a.n_cg * a.splits;
+    a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
+    const uint32_t grid = a.tasks_per_xcd * 8;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(WG), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || p.splits <= 1)
+        return e;
+    const uint64_t count = (uint64_t)g.B * a.stride16;
+    const uint32_t rgrid = (uint32_t)((count + WG - 1) / WG);
+    hipLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream,
+                       static_cast<const uint4 *>(partials), a.out_split16, p.splits, count, a.stride16,
+                       static_cast<uint4 *>(g.out), g.out_pitch / 16);
+    return hipGetLastError();
+}
+
+}  // namespace talek

@@ -1,0 +1,215 @@
+"""GPU parity of the read path against the CPU oracle (bit-exact, tolerance 0).
+
+Every read goes through the C ABI of libtalek_pir.so on the GPU; the expected
+rows come from oracle/ on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2001_08250_amd as pir
+import synth
+from helpers import assert_rows_equal, gpu_available, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _db(D, d, z):
+    n = D.shape[0]
+    db = pir.PirDB(n, d, z)
+    db.load(D)
+    return db
+
+
+TILES = [1, 2, 4, 8, 16, 24, 32]
+
+
+@pytest.mark.parametrize("kind", [pir.KERNEL_MASK, pir.KERNEL_SKIP])
+def test_small_workload_every_tile_schedule(kind):
+    """n = 1024, 4 KiB buckets, B = 8 (plus B = 37 for ragged tiles): all rows."""
+    n, d, z = 1024, 4, 1024
+    D = synth.uniform_db(1001, n, d * z)
+    req8 = synth.bernoulli_requests(2001, 8, n)
+    req37 = synth.bernoulli_requests(2101, 37, n)
+    want8 = oracle.pir_read(D, req8, threads=8)
+    want37 = oracle.pir_read(D, req37, threads=8)
+    with _db(D, d, z) as db:
+        for t in TILES:
+            for u in (4, 8, 16):
+                for s in (1, 0, 7):
+                    say(f"kind={kind} tile={t} unroll={u} splits={s}")
+                    db.set_plan(kind, t, s, u)
+                    assert_rows_equal(db.read(req8), want8, f"B=8 kind={kind} T={t} U={u} S={s}")
+                    assert_rows_equal(db.read(req37), want37, f"B=37 kind={kind} T={t} U={u} S={s}")
+
+
+@pytest.mark.parametrize("p", [0.0, 0.01, 0.5, 0.99, 1.0])
+def test_request_densities(p):
+    n, d, z = 777, 4, 256
+    D = synth.uniform_db(31, n, d * z)
+    req = synth.bernoulli_requests(32, 19, n, p=p)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        for kind in (pir.KERNEL_MASK, pir.KERNEL_SKIP):
+            db.set_plan(kind, 8, 0, 8)
+            assert_rows_equal(db.read(req), want, f"p={p} kind={kind}")
+
+
+def test_one_hot_rows_pin_bit_order_and_boundaries():
+    n, d, z = 1000, 2, 64
+    D = synth.uniform_db(33, n, d * z)
+    idx = [0, 1, 7, 8, 31, 32, 33, 63, 64, 255, 256, 511, 512, 991, 992, 998, 999]
+    req = synth.bits_to_rows(np.eye(n, dtype=bool)[idx])
+    with _db(D, d, z) as db:
+        for kind in (pir.KERNEL_MASK, pir.KERNEL_SKIP):
+            for t in (1, 4, 16):
+                db.set_plan(kind, t, 0, 8)
+                assert_rows_equal(db.read(req), D[idx], f"one-hot kind={kind} T={t}")
+
+
+@pytest.mark.parametrize("n,d,z,B", [(37, 3, 20, 5), (1, 1, 16, 3), (1000, 1, 8, 9), (333, 2, 520, 17),
+                                     (4097, 4, 1024, 33), (300, 2, 4096, 6), (64, 5, 100, 64), (2049, 8, 40, 2)])
+def test_ragged_shapes(n, d, z, B):
+    D = synth.uniform_db(n * 7 + d, n, d * z)
+    req = synth.bernoulli_requests(n + B, B, n)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        assert_rows_equal(db.read(req), want, "auto plan")
+        for kind in (pir.KERNEL_MASK, pir.KERNEL_SKIP):
+            for t in (1, 8, 32):
+                db.set_plan(kind, t, 0, 8)
+                assert_rows_equal(db.read(req), want, f"kind={kind} T={t}")
+
+
+def test_padding_bits_ignored_and_empty_batch():
+    n, d, z = 37, 2, 32
+    D = synth.uniform_db(41, n, d * z)
+    req = synth.bernoulli_requests(42, 4, n, p=0.4)
+    noisy = req.copy()
+    noisy[:, -1] |= 0xE0
+    with _db(D, d, z) as db:
+        assert_rows_equal(db.read(noisy), oracle.pir_read(D, req), "padding bits")
+        assert db.read(np.zeros((0, 5), np.uint8)).shape == (0, d * z)
+
+
+def test_three_server_reconstruction_on_gpu():
+    """l = 3 shares of e_beta answered by the GPU path reconstruct bucket beta."""
+    n, d, z = 2048, 4, 256
+    D = synth.uniform_db(43, n, d * z)
+    with _db(D, d, z) as db:
+        for beta in (0, 5, 1023, 2047):
+            q1 = synth.bernoulli_requests(44 + beta, 1, n)
+            q2 = synth.bernoulli_requests(99 + beta, 1, n)
+            q3 = synth.bits_to_rows(np.eye(n, dtype=bool)[[beta]]) ^ q1 ^ q2
+            R = db.read(np.concatenate([q1, q2, q3]))
+            assert np.array_equal(R[0] ^ R[1] ^ R[2], D[beta])
+
+
+def test_epoch_visibility_and_double_buffering():
+    n, d, z = 256, 2, 64
+    D0 = synth.uniform_db(51, n, d * z)
+    req = synth.bernoulli_requests(52, 7, n)
+    with pir.PirDB(n, d, z) as db:
+        assert not db.read(req).any()                      # empty snapshot is zero
+        db.write_range(0, D0)
+        assert not db.read(req).any()                      # staged, not published
+        db.commit()
+        assert_rows_equal(db.read(req), oracle.pir_read(D0, req), "epoch 1")
+        D1 = D0.copy()
+        for b in (0, 17, 255):
+            D1[b] = synth.uniform_db(60 + b, 1, d * z)[0]
+            db.write_bucket(b, D1[b])
+        D1[17] = synth.uniform_db(99, 1, d * z)[0]         # later write to the same bucket wins
+        db.write_bucket(17, D1[17])
+        assert_rows_equal(db.read(req), oracle.pir_read(D0, req), "still epoch 1")
+        db.commit()
+        assert_rows_equal(db.read(req), oracle.pir_read(D1, req), "epoch 2")
+        D2 = D1.copy()
+        D2[100] = 0
+        db.write_bucket(100, D2[100])
+        db.commit()                                         # back copy was mirrored
+        assert_rows_equal(db.read(req), oracle.pir_read(D2, req), "epoch 3")
+        db.commit()                                         # empty epoch keeps the data
+        assert_rows_equal(db.read(req), oracle.pir_read(D2, req), "epoch 4")
+        assert db.epoch == 4
+
+
+def test_write_errors():
+    with pir.PirDB(16, 2, 8) as db:
+        with pytest.raises(pir.PirError) as e:
+            db.write_bucket(16, np.zeros(16, np.uint8))
+        assert e.value.code == pir.PIR_ERANGE
+        with pytest.raises(pir.PirError):
+            db.write_range(10, np.zeros((7, 16), np.uint8))
+
+
+def test_async_device_api_pitches_and_alignment():
+    import torch
+    n, d, z = 1000, 4, 256          # ceil(n/8) = 125 bytes: not a multiple of 4 -> restaged
+    D = synth.uniform_db(61, n, d * z)
+    req = synth.bernoulli_requests(62, 12, n)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        dev = torch.device("cuda:0")
+        q = torch.from_numpy(req).to(dev)
+        out = torch.zeros((12, d * z), dtype=torch.uint8, device=dev)
+        db.read_async(q, out)
+        torch.cuda.synchronize()
+        assert_rows_equal(out.cpu().numpy(), want, "contiguous")
+        # padded request rows and padded, offset response rows
+        qp = torch.zeros((12, 160), dtype=torch.uint8, device=dev)
+        qp[:, :125] = q
+        big = torch.zeros((12, d * z + 48), dtype=torch.uint8, device=dev)
+        view = big[:, 16:16 + d * z]
+        db.read_async(qp, view)
+        torch.cuda.synchronize()
+        assert_rows_equal(view.cpu().numpy(), want, "pitched")
+        assert not big[:, :16].any() and not big[:, 16 + d * z:].any()
+
+
+def test_stream_of_uneven_batches_matches_single_reads():
+    import torch
+    n, d, z = 4096, 4, 1024
+    D = synth.uniform_db(71, n, d * z)
+    sizes = synth.batch_sizes(72, 23, 1, 300)
+    sizes[3] = 0
+    total = int(sizes.sum())
+    pool = synth.bernoulli_requests(73, 512, n)
+    rng = np.random.default_rng(74)
+    first = np.array([rng.integers(0, 512 - s + 1) for s in sizes], dtype=np.uint64)
+    dev = torch.device("cuda:0")
+    with _db(D, d, z) as db:
+        q = torch.from_numpy(pool).to(dev)
+        out = torch.zeros((total, d * z), dtype=torch.uint8, device=dev)
+        for rep in range(3):                       # first call captures, then graph replays
+            out.zero_()
+            db.read_stream_async(q, sizes, out, req_first=first)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            row = 0
+            for k, s in enumerate(sizes):
+                s = int(s)
+                want = oracle.pir_read(D, pool[int(first[k]):int(first[k]) + s], threads=8)
+                assert_rows_equal(got[row:row + s], want, f"rep {rep} batch {k} (B={s})")
+                row += s
+
+
+def test_tuner_picks_a_correct_plan(tmp_path):
+    n, d, z = 2048, 4, 1024
+    D = synth.uniform_db(81, n, d * z)
+    req = synth.bernoulli_requests(82, 40, n)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        plan, us = db.tune(40, iters=2)
+        say(f"tuned {plan} {us:.1f} us")
+        assert us > 0
+        assert_rows_equal(db.read(req), want, "tuned plan")
+        path = str(tmp_path / "tune.json")
+        assert pir.lib().pir_tune_save(path.encode()) == 0
+        assert pir.lib().pir_tune_load(path.encode()) == 0
