@@ -1,10 +1,17 @@
-"""Benchmark of the XOR-PIR server read path on one MI355X.
+"""Benchmark of the XOR-PIR server path on one MI355X.
 
 Default workload: n = 65,536 buckets of 4 x 1 KiB, filled by blocked-cuckoo
-insertion of 200,000 synthetic messages, answering batches of B = 256
-Bernoulli(1/2) request vectors. Prints ONE JSON line.
+insertion of 200,000 synthetic messages (load 0.763), answering batches of
+B = 256 Bernoulli(1/2) request vectors.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4a|c4b]
+One step = one served batch through the whole server path: ceil(B/10) new
+Write requests (cuckoo insert with FIFO garbage collection + 6 interest bits
+each) staged and published as a new epoch, then the batch of B reads answered
+on that snapshot, then the global interest vector fetched. Inputs are
+resident (requests and writes prepared before the timed region). Prints ONE
+JSON line on stdout.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4a|c4b|c3b] [--step full|read]
 """
 from __future__ import annotations
 
@@ -24,6 +31,8 @@ from synth import configs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit VALU lane-ops per second: 39.3 T
+INTEREST_K = 6
+WRITE_FRAC = 0.1
 
 
 def log(*a):
@@ -35,51 +44,16 @@ def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
     return bits.sum(axis=1, dtype=np.int64)
 
 
-def build_db(w, pir):
-    """Database of the workload, published on the GPU. Returns (db, cuckoo or None, host D or None)."""
-    db = pir.PirDB(w.n, w.d, w.z)
-    if w.fill == "cuckoo":
-        ids, b1, b2, pay = synth.write_ops(w.cuckoo_seed, w.cuckoo_items, w.n, w.z)
-        ck = pir.Cuckoo(db, capacity=w.cuckoo_items, seed=w.cuckoo_seed, max_kicks=configs.CUCKOO_MAX_KICKS)
-        status, _ = ck.insert_many(ids, b1, b2, pay)
-        failed = int((status != 0).sum())
-        ck.stage()
-        db.commit()
-        return db, ck, (ids, b1, b2, pay), failed
-    D = synth.uniform_db(w.db_seed, w.n, w.bucket_bytes, threads=16)
-    db.load(D)
-    return db, None, D, 0
-
-
-def cpu_baseline(w, writes_or_D, req, got, sample_rows, threads):
-    """Time the oracle on a bounded sample of the same workload and check parity."""
-    import oracle
-    if w.fill == "cuckoo":
-        ids, b1, b2, pay = writes_or_D
-        ref = oracle.Cuckoo(w.n, w.d, w.z, capacity=w.cuckoo_items, seed=w.cuckoo_seed,
-                            max_kicks=configs.CUCKOO_MAX_KICKS)
-        ref.insert_many(ids, b1, b2, pay)
-        D = ref.table()
-    else:
-        D = writes_or_D
-    rows = np.arange(min(sample_rows, req.shape[0]))
-    t0 = time.perf_counter()
-    want = oracle.pir_read(D, req[rows], threads=threads)
-    dt = time.perf_counter() - t0
-    parity = bool(np.array_equal(want, got[rows]))
-    return {"value": len(rows) / dt, "unit": "reads/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(rows)} of the {req.shape[0]} request rows of the same batch over the full "
-                      f"{w.db_bytes >> 20} MiB database, plain C byte loop (gcc -O2), {threads} threads"}, parity, D
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4a", "c4b", "c3b"])
+    ap.add_argument("--step", default="", choices=["", "full", "read"],
+                    help="full = writes + commit + read + interest fetch (default for cuckoo workloads)")
     ap.add_argument("--B", type=int, default=0, help="override the batch size")
-    ap.add_argument("--kind", type=int, default=0, help="force kernel family (1 mask, 2 skip, 3 m4r)")
+    ap.add_argument("--kind", type=int, default=0, help="force kernel family (1 mask, 2 skip, 3 four-russians)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
@@ -97,13 +71,41 @@ def main():
     import paper_2001_08250_amd as pir
 
     torch.cuda.set_device(0)
-    w = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B,
-         "c3b": configs.C3}[args.workload]
+    w = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B, "c3b": configs.C3}[args.workload]
     B = args.B or w.B or 1024
-    log(f"[bench] workload {w.name} n={w.n} d={w.d} z={w.z} B={B}")
+    full = (args.step or ("full" if w.fill == "cuckoo" else "read")) == "full"
+    K, W = args.steps, args.warmup
+    log(f"[bench] workload {w.name} n={w.n} d={w.d} z={w.z} B={B} step={'full' if full else 'read'}")
+
+    # ---- database -------------------------------------------------------
     t = time.perf_counter()
-    db, ck, src, failed = build_db(w, pir)
-    log(f"[bench] database ready in {time.perf_counter() - t:.1f}s (cuckoo failures: {failed})")
+    db = pir.PirDB(w.n, w.d, w.z)
+    db.interest_config(1 << 20, 8)
+    ck = None
+    pre = None
+    if w.fill == "cuckoo":
+        pre = synth.write_ops(w.cuckoo_seed, w.cuckoo_items, w.n, w.z)
+        ck = pir.Cuckoo(db, capacity=w.cuckoo_items, seed=w.cuckoo_seed, max_kicks=configs.CUCKOO_MAX_KICKS)
+        status, _ = ck.insert_many(*pre)
+        ck.stage()
+        D0 = None
+    else:
+        D0 = synth.uniform_db(w.db_seed, w.n, w.bucket_bytes, threads=16)
+        db.write_range(0, D0)
+    db.commit()
+    log(f"[bench] database ready in {time.perf_counter() - t:.1f}s")
+
+    # ---- per-step writes (prepared before timing) ---------------------------
+    nw = max(1, -(-B // int(1 / WRITE_FRAC))) if full else 0
+    total_w = nw * (W + K)
+    if full:
+        if ck is not None:
+            wr = synth.write_ops(w.cuckoo_seed + 17, total_w, w.n, w.z, id_offset_seed=w.cuckoo_seed + 18)
+        else:
+            wr = (None, synth.uniform_indices(w.req_seed + 5, total_w, w.n), None,
+                  synth.uniform_bytes(w.req_seed + 6, total_w * w.bucket_bytes).reshape(total_w, w.bucket_bytes))
+        ipos = synth.interest_positions(w.req_seed + 7, total_w, INTEREST_K, 1 << 20)
+
     req = synth.bernoulli_requests(w.req_seed, B, w.n)
     if args.kind:
         db.set_plan(args.kind, args.tile, args.splits, args.unroll)
@@ -116,32 +118,55 @@ def main():
     dev = torch.device("cuda:0")
     q = torch.from_numpy(req).to(dev)
     out = torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev)
+    iv = torch.empty(((1 << 20) // 8,), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    L = pir.lib()
+    sh = int(stream.cuda_stream)
+
+    def do_writes(k):
+        sl = slice(k * nw, (k + 1) * nw)
+        if ck is not None:
+            ck.insert_many(wr[0][sl], wr[1][sl], wr[2][sl], wr[3][sl])
+            ck.stage()
+        else:
+            for i in range(sl.start, sl.stop):
+                db.write_bucket(int(wr[1][i]), wr[3][i])
+        db.interest_add(ipos[sl])
+        db.commit()
+
+    def step(k, ev=None):
+        if full:
+            do_writes(k)
+        if ev is not None:
+            ev[0].record(stream)
         db.read_async(q, out)
+        if ev is not None:
+            ev[1].record(stream)
+        if full:
+            L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), sh)
+
+    for k in range(W):
+        step(k)
     torch.cuda.synchronize()
-    K = args.steps
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        evs[k][0].record(stream)
-        db.read_async(q, out)
-        evs[k][1].record(stream)
+        step(W + k, evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     got = out.cpu().numpy()
+    got_iv = iv.cpu().numpy()
 
     ms_per_step = 1000.0 * wall / K
     value = B * K / wall
     pops = popcount_rows(req, w.n)
-    xor_ops = float(pops.sum()) * (w.bucket_bytes / 4)            # plain dword-XOR count per launch
+    xor_ops = float(pops.sum()) * (w.bucket_bytes / 4)            # plain dword-XOR count per read launch
     alg_bytes = w.n * w.bucket_bytes + B * ((w.n + 7) // 8) + B * w.bucket_bytes
     t_kernel = kern_ms / 1000.0
     hbm_achieved = alg_bytes / t_kernel / 1e9
     alu_achieved = xor_ops / t_kernel / 1e12
-    # the bound is whichever roofline the algorithmic work hits first
     t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
     t_alu = xor_ops / (VALU_PEAK_TOPS * 1e12)
     if t_alu >= t_hbm:
@@ -150,16 +175,42 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None}
-    roof["kernel_ms"] = round(kern_ms, 4)
-    roof["hbm_gbs_alg"] = round(hbm_achieved, 1)
-    roof["plain_xor_tops"] = round(alu_achieved, 3)
+    roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
+                plain_xor_tops=round(alu_achieved, 3))
 
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
+        import oracle
         threads = min(16, os.cpu_count() or 1)
-        cpu, parity, _ = cpu_baseline(w, src, req, got, args.cpu_rows, threads)
-        log(f"[bench] oracle {cpu['value']:.1f} reads/s on {threads} threads; parity={parity}")
+        # the oracle rebuilds the final snapshot from the same writes
+        if ck is not None:
+            ref = oracle.Cuckoo(w.n, w.d, w.z, capacity=w.cuckoo_items, seed=w.cuckoo_seed,
+                                max_kicks=configs.CUCKOO_MAX_KICKS)
+            ref.insert_many(*pre)
+            if full:
+                ref.insert_many(wr[0][:total_w], wr[1][:total_w], wr[2][:total_w], wr[3][:total_w])
+            D = ref.table()
+        else:
+            D = D0
+            if full:
+                D = D0.copy()
+                for i in range(total_w):
+                    D[int(wr[1][i])] = wr[3][i]
+        rows = np.arange(min(args.cpu_rows, B))
+        t1 = time.perf_counter()
+        want = oracle.pir_read(D, req[rows], threads=threads)
+        dt = time.perf_counter() - t1
+        parity = bool(np.array_equal(want, got[rows]))
+        if full:
+            last = W + K - 1
+            epochs = [np.zeros(0, np.uint32)] + [ipos[k * nw:(k + 1) * nw].reshape(-1) for k in range(W + K)]
+            want_iv = oracle.interest_window(1 << 20, epochs, last + 1, 8)
+            parity = parity and bool(np.array_equal(want_iv, got_iv))
+        cpu = {"value": round(len(rows) / dt, 2), "unit": "reads/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(rows)} of the {B} request rows of the last batch over the full "
+                         f"{w.db_bytes >> 20} MiB snapshot, plain C byte loop (gcc -O2), {threads} threads"}
+        log(f"[bench] oracle {cpu['value']} reads/s on {threads} threads; parity={parity}")
 
     line = {
         "metric": "PIR bucket-reads/sec",
@@ -167,7 +218,7 @@ def main():
         "unit": "reads/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
+        "warmup": W,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -175,6 +226,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "B": B,
+                   "step": "writes+commit+read+interest" if full else "read",
+                   "writes_per_step": nw,
                    "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll},
                    "parallelism": "single-gpu"},
         "roofline": roof,

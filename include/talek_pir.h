@@ -260,6 +260,73 @@ int pir_cuckoo_table(const pir_cuckoo *c, uint8_t *out, uint64_t out_bytes);
 int pir_cuckoo_slots(const pir_cuckoo *c, uint64_t *ids, uint8_t *occupied);
 uint64_t pir_cuckoo_live(const pir_cuckoo *c);
 
+/* ----------------------------------------------------------------- serving */
+
+/*
+ * Serving loop: an open-loop stream of timed reads and writes is served
+ * against db (and its cuckoo working copy `table`) with continuous batching
+ * (section "Evaluation": reads are batched and forwarded to the GPU, writes
+ * go to the DRAM working copy and are snapshotted into the GPU periodically;
+ * section "Private Notifications": each read comes back with the current
+ * global interest vector).
+ *   - A read arriving at time t is admitted once a memory slot is free (each
+ *     in-flight read holds ceil(n/8) request bytes and one response bucket of
+ *     device memory; mem_budget bounds the total). Admitted reads queue.
+ *   - Whenever one of `lanes` device lanes (each its own HIP stream and
+ *     buffers) is free, up to max_batch queued reads leave as one batch: their
+ *     request rows are gathered from pinned host memory by a kernel, answered
+ *     by the tuned read kernel, and the responses plus the published global
+ *     interest vector are copied back. Batches on different lanes overlap on
+ *     the device; reads arriving meanwhile join the next batch.
+ *   - Every epoch_s seconds the writes that have arrived are applied to the
+ *     cuckoo table (with their interest bits) and published (pir_epoch_commit).
+ *     A read is answered from the snapshot published when its batch launched;
+ *     read_epoch reports which.
+ *   - max_batch = 1 gives the one-launch-per-read baseline.
+ * Latency of a read = device completion of its batch (response and interest
+ * vector in host memory) minus its arrival time.
+ */
+typedef struct pir_serve_config {
+    uint32_t max_batch;      /* reads per launch, >= 1 */
+    uint32_t lanes;          /* batches in flight, 1..8 */
+    uint64_t mem_budget;     /* device bytes for in-flight reads; 0 = lanes * max_batch reads */
+    double epoch_s;          /* write publication period, > 0 */
+    uint32_t interest_k;     /* interest positions per write (0 = none) */
+    uint32_t reserved;
+} pir_serve_config;
+
+typedef struct pir_serve_trace {
+    uint64_t n_reads;
+    const double *read_t;          /* arrival times in seconds, nondecreasing */
+    const uint32_t *read_row;      /* pool row carried by each read */
+    const uint8_t *req_pool;       /* pool_rows request rows of ceil(n/8) bytes */
+    uint64_t pool_rows;
+    uint64_t n_writes;
+    const double *write_t;         /* arrival times, nondecreasing */
+    const uint64_t *write_id;
+    const uint64_t *write_beta1;
+    const uint64_t *write_beta2;
+    const uint8_t *write_payload;  /* n_writes x msg_bytes */
+    const uint32_t *write_interest; /* n_writes x interest_k positions (< m_bits) */
+} pir_serve_trace;
+
+typedef struct pir_serve_result {
+    /* per-read outputs (each may be NULL) */
+    double *latency_s;             /* n_reads */
+    uint64_t *read_epoch;          /* n_reads: epoch that answered the read */
+    uint64_t n_probe;              /* reads whose response is returned */
+    const uint64_t *probe;         /* their indices, increasing */
+    uint8_t *probe_resp;           /* n_probe x (d * msg_bytes) */
+    uint8_t *probe_iv;             /* n_probe x ceil(m_bits / 8), or NULL */
+    uint64_t *write_epoch;         /* n_writes: epoch that published the write (UINT64_MAX: never) */
+    /* summary, filled by the call */
+    uint64_t completed, batches, epochs, writes_applied, writes_failed, max_queue;
+    double wall_s, reads_per_s, p50_s, p99_s, max_s, mean_batch;
+} pir_serve_result;
+
+int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
+                  const pir_serve_trace *trace, pir_serve_result *res);
+
 #ifdef __cplusplus
 }
 #endif

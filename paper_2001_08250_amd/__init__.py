@@ -40,6 +40,34 @@ class pir_plan(ctypes.Structure):
         return f"pir_plan(kind={self.kind}, tile={self.tile}, splits={self.splits}, unroll={self.unroll})"
 
 
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class pir_serve_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("lanes", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64),
+                ("epoch_s", ctypes.c_double), ("interest_k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class pir_serve_trace(ctypes.Structure):
+    _fields_ = [("n_reads", ctypes.c_uint64), ("read_t", _dp), ("read_row", ctypes.POINTER(ctypes.c_uint32)),
+                ("req_pool", ctypes.POINTER(ctypes.c_uint8)), ("pool_rows", ctypes.c_uint64),
+                ("n_writes", ctypes.c_uint64), ("write_t", _dp), ("write_id", ctypes.POINTER(ctypes.c_uint64)),
+                ("write_beta1", ctypes.POINTER(ctypes.c_uint64)), ("write_beta2", ctypes.POINTER(ctypes.c_uint64)),
+                ("write_payload", ctypes.POINTER(ctypes.c_uint8)),
+                ("write_interest", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class pir_serve_result(ctypes.Structure):
+    _fields_ = [("latency_s", _dp), ("read_epoch", ctypes.POINTER(ctypes.c_uint64)), ("n_probe", ctypes.c_uint64),
+                ("probe", ctypes.POINTER(ctypes.c_uint64)), ("probe_resp", ctypes.POINTER(ctypes.c_uint8)),
+                ("probe_iv", ctypes.POINTER(ctypes.c_uint8)), ("write_epoch", ctypes.POINTER(ctypes.c_uint64)),
+                ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("epochs", ctypes.c_uint64), ("writes_applied", ctypes.c_uint64),
+                ("writes_failed", ctypes.c_uint64), ("max_queue", ctypes.c_uint64), ("wall_s", ctypes.c_double),
+                ("reads_per_s", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+
+
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -79,6 +107,8 @@ SIGNATURES = {
     "pir_cuckoo_table": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_cuckoo_slots": (ctypes.c_int, [_vp, _u64p, _u8p]),
     "pir_cuckoo_live": (_u64, [_vp]),
+    "pir_serve_run": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(pir_serve_config), ctypes.POINTER(pir_serve_trace),
+                                     ctypes.POINTER(pir_serve_result)]),
 }
 
 _lib = None
@@ -260,6 +290,68 @@ class PirDB:
         out = np.zeros((m + 7) // 8, dtype=np.uint8)
         _check(self._L.pir_interest_vector(self.h, _ptr(out), out.size), "pir_interest_vector")
         return out
+
+
+def serve(db: "PirDB", table: "Cuckoo | None", *, read_t, read_row, req_pool, write_t=None, writes=None,
+          write_interest=None, max_batch=512, lanes=2, mem_budget=0, epoch_s=1.0, probe=None, with_iv=False):
+    """Run the native serving loop (pir_serve_run) on a timed trace.
+
+    writes = (ids, beta1, beta2, payload) arrays; write_interest uint32 [n_writes, k].
+    Returns a dict with the summary, per-read latency/epoch and probe responses.
+    """
+    L = lib()
+    read_t = np.ascontiguousarray(read_t, dtype=np.float64)
+    read_row = np.ascontiguousarray(read_row, dtype=np.uint32)
+    req_pool = np.ascontiguousarray(req_pool, dtype=np.uint8)
+    tr = pir_serve_trace()
+    tr.n_reads = read_t.size
+    tr.read_t = read_t.ctypes.data_as(_dp)
+    tr.read_row = _ptr(read_row, ctypes.c_uint32)
+    tr.req_pool = _ptr(req_pool)
+    tr.pool_rows = req_pool.shape[0]
+    keep = [read_t, read_row, req_pool]
+    k = 0
+    if writes is not None and len(writes[0]):
+        ids, b1, b2, pay = (np.ascontiguousarray(writes[0], dtype=np.uint64),
+                            np.ascontiguousarray(writes[1], dtype=np.uint64),
+                            np.ascontiguousarray(writes[2], dtype=np.uint64),
+                            np.ascontiguousarray(writes[3], dtype=np.uint8))
+        wt = np.ascontiguousarray(write_t, dtype=np.float64)
+        tr.n_writes = ids.size
+        tr.write_t = wt.ctypes.data_as(_dp)
+        tr.write_id = _ptr(ids, ctypes.c_uint64)
+        tr.write_beta1 = _ptr(b1, ctypes.c_uint64)
+        tr.write_beta2 = _ptr(b2, ctypes.c_uint64)
+        tr.write_payload = _ptr(pay)
+        keep += [ids, b1, b2, pay, wt]
+        if write_interest is not None:
+            wi = np.ascontiguousarray(write_interest, dtype=np.uint32)
+            k = wi.shape[1] if wi.ndim == 2 else 0
+            tr.write_interest = _ptr(wi, ctypes.c_uint32)
+            keep.append(wi)
+    cfg = pir_serve_config(max_batch, lanes, mem_budget, epoch_s, k, 0)
+    res = pir_serve_result()
+    lat = np.zeros(read_t.size, dtype=np.float64)
+    ep = np.zeros(read_t.size, dtype=np.uint64)
+    res.latency_s = lat.ctypes.data_as(_dp)
+    res.read_epoch = _ptr(ep, ctypes.c_uint64)
+    probe = np.zeros(0, np.uint64) if probe is None else np.ascontiguousarray(np.sort(probe), dtype=np.uint64)
+    presp = np.zeros((probe.size, db.bucket_bytes), dtype=np.uint8)
+    piv = np.zeros((probe.size, (getattr(db, "m_bits", 1 << 20) + 7) // 8), dtype=np.uint8) if with_iv else None
+    res.n_probe = probe.size
+    res.probe = _ptr(probe, ctypes.c_uint64)
+    res.probe_resp = _ptr(presp)
+    if piv is not None:
+        res.probe_iv = _ptr(piv)
+    wep = np.zeros(tr.n_writes, dtype=np.uint64)
+    res.write_epoch = _ptr(wep, ctypes.c_uint64)
+    _check(L.pir_serve_run(db.h, table.h if table is not None else None, ctypes.byref(cfg), ctypes.byref(tr),
+                           ctypes.byref(res)), "pir_serve_run")
+    out = {f: getattr(res, f) for f, _ in pir_serve_result._fields_
+           if f not in ("latency_s", "read_epoch", "n_probe", "probe", "probe_resp", "probe_iv", "write_epoch")}
+    out.update(latency_s=lat, read_epoch=ep, probe=probe, probe_resp=presp, probe_iv=piv, write_epoch=wep)
+    del keep
+    return out
 
 
 class Cuckoo:

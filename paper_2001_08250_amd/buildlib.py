@@ -22,6 +22,7 @@ SOURCES = [
     "cuckoo.cpp",
     "tune.cpp",
     "stream.cpp",
+    "serve.cpp",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value", f"-I{os.path.join(ROOT, 'include')}"]

@@ -58,6 +58,88 @@ __global__ __launch_bounds__(WG) void or_rows_kernel(uint32_t *__restrict__ out,
     }
 }
 
+// Request staging: Qt[w][r] = word w of request row r (bits >= n cleared),
+// rows r in [B, Bp) zero. 64 x 64 word tiles transposed through LDS so both
+// the reads (along a row) and the writes (along a word column) coalesce.
+__global__ __launch_bounds__(WG) void transpose_requests_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
+                                                                uint32_t B, uint64_t n, uint32_t *__restrict__ Qt,
+                                                                uint32_t Bp)
+{
+    __shared__ uint32_t tile[64][65];
+    const uint64_t nwords = (n + 31) >> 5;
+    const uint64_t w0 = (uint64_t)blockIdx.x * 64;
+    const uint32_t r0 = blockIdx.y * 64;
+    const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;
+    for (uint32_t i = ty; i < 64; i += WG / 64) {
+        const uint32_t r = r0 + i;
+        const uint64_t w = w0 + tx;
+        uint32_t v = 0;
+        if (r < B && w < nwords) {
+            v = Q[(uint64_t)r * qpitch_w + w];
+            if (((w + 1) << 5) > n)
+                v &= (1u << (n & 31u)) - 1u;
+        }
+        tile[i][tx] = v;
+    }
+    __syncthreads();
+    for (uint32_t i = ty; i < 64; i += WG / 64) {
+        const uint64_t w = w0 + i;
+        const uint32_t r = r0 + tx;
+        if (w < nwords && r < Bp)
+            Qt[w * Bp + r] = tile[tx][i];
+    }
+}
+
+// Four-Russians staging: Qs[g * Bp + r] = (byte g of request row r) << 8,
+// i.e. the LDS byte offset of that request's table entry for bucket group g
+// (bits >= n cleared, rows B <= r < Bp zero).
+__global__ __launch_bounds__(WG) void stage_group_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
+                                                                 uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
+                                                                 uint32_t Bp)
+{
+    __shared__ uint32_t tile[64][65];
+    const uint64_t nwords = (n + 31) >> 5;
+    const uint64_t w0 = (uint64_t)blockIdx.x * 64;
+    const uint32_t r0 = blockIdx.y * 64;
+    const uint32_t tx = threadIdx.x & 63u, ty = threadIdx.x >> 6;
+    for (uint32_t i = ty; i < 64; i += WG / 64) {
+        const uint32_t r = r0 + i;
+        const uint64_t w = w0 + tx;
+        uint32_t v = 0;
+        if (r < B && w < nwords) {
+            v = Q[(uint64_t)r * qpitch_w + w];
+            if (((w + 1) << 5) > n)
+                v &= (1u << (n & 31u)) - 1u;
+        }
+        tile[i][tx] = v;
+    }
+    __syncthreads();
+    for (uint32_t i = ty; i < 64; i += WG / 64) {
+        const uint64_t w = w0 + i;
+        const uint32_t r = r0 + tx;
+        if (w < nwords && r < Bp) {
+            const uint32_t v = tile[tx][i];
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k)
+                Qs[(w * 4 + k) * Bp + r] = ((v >> (8 * k)) & 0xffu) << 8;
+        }
+    }
+}
+
+// dst row i = src row rows[i] for i < count (row16 uint4 per row). Used by
+// the serving loop to pull the request rows of a batch straight out of
+// pinned host memory (src and rows are host-mapped).
+__global__ __launch_bounds__(WG) void gather_rows_kernel(uint4 *__restrict__ dst, uint64_t dst_pitch16,
+                                                         const uint4 *__restrict__ src, uint64_t src_pitch16,
+                                                         const uint32_t *__restrict__ rows, uint32_t row16)
+{
+    const uint64_t i = blockIdx.x;
+    const uint4 *s = src + (uint64_t)rows[i] * src_pitch16;
+    uint4 *d = dst + i * dst_pitch16;
+    for (uint32_t c = threadIdx.x; c < row16; c += WG)
+        d[c] = s[c];
+}
+
 uint32_t grid_for(uint64_t items)
 {
     uint64_t g = (items + WG - 1) / WG;
@@ -85,6 +167,41 @@ hipError_t launch_copy_rows(void *dst, const void *src, const uint64_t *idx, uin
         return hipSuccess;
     hipLaunchKernelGGL(scatter_rows_kernel, dim3((uint32_t)count), dim3(WG), 0, stream, static_cast<uint4 *>(dst),
                        static_cast<const uint4 *>(src), idx, stride / 16, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_requests(const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t *Qt,
+                                     uint32_t Bp, hipStream_t stream)
+{
+    const uint64_t nwords = (n + 31) / 32;
+    if (nwords == 0 || Bp == 0)
+        return hipSuccess;
+    dim3 grid((uint32_t)((nwords + 63) / 64), (Bp + 63) / 64);
+    hipLaunchKernelGGL(transpose_requests_kernel, grid, dim3(WG), 0, stream, static_cast<const uint32_t *>(Q),
+                       qpitch / 4, B, n, Qt, Bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_group_offsets(const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t *Qs,
+                                      uint32_t Bp, hipStream_t stream)
+{
+    const uint64_t nwords = (n + 31) / 32;
+    if (nwords == 0 || Bp == 0)
+        return hipSuccess;
+    dim3 grid((uint32_t)((nwords + 63) / 64), (Bp + 63) / 64);
+    hipLaunchKernelGGL(stage_group_offsets_kernel, grid, dim3(WG), 0, stream, static_cast<const uint32_t *>(Q),
+                       qpitch / 4, B, n, Qs, Bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(void *dst, uint64_t dst_pitch, const void *src, uint64_t src_pitch,
+                              const uint32_t *rows, uint32_t count, uint64_t row_bytes, hipStream_t stream)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(count), dim3(WG), 0, stream, static_cast<uint4 *>(dst),
+                       dst_pitch / 16, static_cast<const uint4 *>(src), src_pitch / 16, rows,
+                       (uint32_t)((row_bytes + 15) / 16));
     return hipGetLastError();
 }
 

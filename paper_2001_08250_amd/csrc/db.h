@@ -90,6 +90,14 @@ struct pir_db {
     uint64_t pos_dev_cap = 0;
     uint32_t *pos_host = nullptr;      // pinned
     uint64_t pos_host_cap = 0;
+
+    // Each pinned upload buffer is free for the host again once its event
+    // (recorded after the copy that reads it) has completed: 0 = staged rows
+    // and indices, 1 = interest positions, 2 = mirror indices.
+    hipEvent_t upload_ev[3] = {nullptr, nullptr, nullptr};
+    bool upload_pending[3] = {false, false, false};
+    uint64_t *mirror_idx_host = nullptr;  // pinned
+    uint64_t mirror_idx_cap = 0;
 };
 
 namespace talek {

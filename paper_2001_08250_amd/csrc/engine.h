@@ -55,6 +55,22 @@ hipError_t launch_scatter_rows(void *dst, const void *src, const uint64_t *idx, 
 hipError_t launch_copy_rows(void *dst, const void *src, const uint64_t *idx, uint64_t count,
                             uint64_t stride, hipStream_t stream);
 
+// --- request staging ------------------------------------------------------
+// Qt[w * Bp + r] = 32-bit word w of request row r with bits >= n cleared;
+// rows B <= r < Bp are zero. Bp % 64 == 0.
+hipError_t launch_transpose_requests(const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t *Qt,
+                                     uint32_t Bp, hipStream_t stream);
+
+// Qs[g * Bp + r] = (byte g of request row r) << 8 for every 8-bucket group g
+// (4 * ceil(n / 32) groups); rows B <= r < Bp are zero. Bp % 64 == 0.
+hipError_t launch_stage_group_offsets(const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t *Qs,
+                                      uint32_t Bp, hipStream_t stream);
+
+// dst row i = src row rows[i], i < count; pitches multiples of 16, rows of
+// round_up(row_bytes, 16) bytes are copied. src and rows may be host-mapped.
+hipError_t launch_gather_rows(void *dst, uint64_t dst_pitch, const void *src, uint64_t src_pitch,
+                              const uint32_t *rows, uint32_t count, uint64_t row_bytes, hipStream_t stream);
+
 // --- interest vector -----------------------------------------------------
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);           // bytes % 4 == 0
 hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count, hipStream_t stream);

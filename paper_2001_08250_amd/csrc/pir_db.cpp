@@ -122,6 +122,25 @@ int ensure_back(pir_db *db)
     return PIR_OK;
 }
 
+enum { UP_STAGE = 0, UP_POS = 1, UP_MIRROR = 2 };
+
+// Block until pinned upload buffer `which` is no longer read by a queued copy.
+int wait_upload(pir_db *db, int which)
+{
+    if (!db->upload_pending[which])
+        return PIR_OK;
+    HIP_TRY(hipEventSynchronize(db->upload_ev[which]));
+    db->upload_pending[which] = false;
+    return PIR_OK;
+}
+
+int note_upload(pir_db *db, int which)
+{
+    HIP_TRY(hipEventRecord(db->upload_ev[which], db->stream));
+    db->upload_pending[which] = true;
+    return PIR_OK;
+}
+
 void mark_dirty(pir_db *db, uint64_t b)
 {
     if (db->all_dirty || db->dirty_mark[b])
@@ -144,7 +163,7 @@ int flush_stage(pir_db *db)
                            db->stream));
     HIP_TRY(launch_scatter_rows(db->buf[db->front ^ 1], db->stage_dev, static_cast<uint64_t *>(db->stage_idx_dev),
                                 rows, db->stride, db->stream));
-    HIP_TRY(hipStreamSynchronize(db->stream));  // staging rows are reused next
+    PIR_TRY(note_upload(db, UP_STAGE));  // the staging rows are refilled only after this
     for (uint64_t i = 0; i < rows; ++i)
         mark_dirty(db, db->stage_idx_host[i]);
     db->stage_rows = 0;
@@ -161,6 +180,8 @@ int stage_row(pir_db *db, uint64_t bucket, const uint8_t *data)
     } else {
         if (db->stage_rows == db->stage_cap)
             PIR_TRY(flush_stage(db));
+        if (db->stage_rows == 0)
+            PIR_TRY(wait_upload(db, UP_STAGE));
         slot = db->stage_rows++;
         db->stage_slot.emplace(bucket, slot);
         db->stage_idx_host[slot] = bucket;
@@ -236,6 +257,11 @@ void free_db(pir_db *db)
         hipHostFree(db->pos_host);
     if (db->published)
         hipEventDestroy(db->published);
+    for (int i = 0; i < 3; ++i)
+        if (db->upload_ev[i])
+            hipEventDestroy(db->upload_ev[i]);
+    if (db->mirror_idx_host)
+        hipHostFree(db->mirror_idx_host);
     if (db->stream)
         hipStreamDestroy(db->stream);
     if (db->capture_stream)
@@ -295,6 +321,11 @@ int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
             break;
         }
         if (hipEventCreateWithFlags(&db->published, hipEventDisableTiming) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        for (int i = 0; i < 3 && rc == PIR_OK; ++i)
+            if (hipEventCreateWithFlags(&db->upload_ev[i], hipEventDisableTiming) != hipSuccess)
+                rc = PIR_EDEVICE;
+        if (rc != PIR_OK)
+            break;
         void *p = nullptr;
         if (hipMalloc(&p, n * stride) != hipSuccess) { rc = PIR_ENOMEM; break; }
         db->buf[0] = static_cast<uint8_t *>(p);
@@ -396,6 +427,7 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 
     // interest vector: the open epoch's delta replaces the oldest ring slot;
     // the new global vector (OR of the window) goes with the back copy.
+    PIR_TRY(wait_upload(db, UP_POS));
     if (db->pos_pending.size() > db->pos_host_cap) {
         if (db->pos_host)
             hipHostFree(db->pos_host);
@@ -412,6 +444,7 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
         memcpy(db->pos_host, db->pos_pending.data(), npos * 4);
         PIR_TRY(ensure_device(&db->pos_dev, &db->pos_dev_cap, npos * 4));
         HIP_TRY(hipMemcpyAsync(db->pos_dev, db->pos_host, npos * 4, hipMemcpyHostToDevice, db->stream));
+        PIR_TRY(note_upload(db, UP_POS));
     }
     // The back copy's vector may still be read by async readers of the
     // buffer it belonged to before the last swap.
@@ -431,7 +464,6 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
         HIP_TRY(hipMemcpyAsync(db->iv_global[db->front], db->iv_global[back], db->iv_words * 4,
                                hipMemcpyDeviceToDevice, db->stream));
         HIP_TRY(hipEventRecord(db->published, db->stream));
-        HIP_TRY(hipStreamSynchronize(db->stream));
         db->epoch++;
         if (epoch_out)
             *epoch_out = db->epoch;
@@ -449,13 +481,27 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
                                db->stream));
     } else if (!db->dirty.empty()) {
         const uint64_t cnt = db->dirty.size();
+        PIR_TRY(wait_upload(db, UP_MIRROR));
+        if (cnt > db->mirror_idx_cap) {
+            if (db->mirror_idx_host)
+                hipHostFree(db->mirror_idx_host);
+            db->mirror_idx_host = nullptr;
+            db->mirror_idx_cap = 0;
+            void *p = nullptr;
+            if (hipHostMalloc(&p, cnt * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+                return PIR_ENOMEM;
+            db->mirror_idx_host = static_cast<uint64_t *>(p);
+            db->mirror_idx_cap = cnt;
+        }
+        memcpy(db->mirror_idx_host, db->dirty.data(), cnt * sizeof(uint64_t));
         PIR_TRY(ensure_device(&db->stage_idx_dev, &db->stage_idx_dev_cap, cnt * sizeof(uint64_t)));
-        HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->dirty.data(), cnt * sizeof(uint64_t), hipMemcpyHostToDevice,
-                               db->stream));
+        HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->mirror_idx_host, cnt * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, db->stream));
+        PIR_TRY(note_upload(db, UP_MIRROR));
         HIP_TRY(launch_copy_rows(db->buf[old_front], db->buf[db->front],
                                  static_cast<uint64_t *>(db->stage_idx_dev), cnt, db->stride, db->stream));
     }
-    HIP_TRY(hipStreamSynchronize(db->stream));
+    // no host wait: the rest of the commit runs stream-ordered on the device
     for (uint64_t b : db->dirty)
         db->dirty_mark[b] = 0;
     db->dirty.clear();

@@ -10,6 +10,7 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
 bool m4r_plan_supported(const Plan &p);
 hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
 uint32_t m4r_tasks(const ReadGeom &g, const Plan &p);
+uint64_t m4r_staging_bytes(const ReadGeom &g);
 
 namespace {
 
@@ -34,25 +35,29 @@ bool plan_supported(const Plan &p)
 
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
 {
-    if (p.splits <= 1)
-        return 0;
-    return (uint64_t)p.splits * g.B * g.stride;
+    uint64_t bytes = p.splits <= 1 ? 0 : (uint64_t)p.splits * g.B * g.stride;
+    if (p.kind == KIND_M4R)
+        bytes += m4r_staging_bytes(g);
+    return bytes;
 }
 
 Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
     if (p.kind == KIND_AUTO)
-        p.kind = KIND_MASK;
+        p.kind = g.B >= 64 ? KIND_M4R : KIND_MASK;
     const uint64_t nwords = (g.n + 31) / 32;
     const uint32_t stride16 = (uint32_t)(g.stride / 16);
     uint64_t units;  // independent workgroup tasks per split
+    uint64_t per_cu = 8;  // workgroups per CU to aim for
     if (p.kind == KIND_M4R) {
+        // tile = requests per wave, unroll = waves per workgroup
         if (p.tile == 0)
-            p.tile = g.B <= 128 ? 32 : 64;
+            p.tile = 32;
         if (p.unroll == 0)
-            p.unroll = 8;
+            p.unroll = g.B >= 256 ? 8 : 4;
         units = m4r_tasks(g, Plan{p.kind, p.tile, 1, p.unroll});
+        per_cu = 2;  // one 128 KiB LDS table pair per CU at a time
     } else {
         if (p.tile == 0)
             p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;
@@ -63,7 +68,7 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         units = n_rt * n_cg;
     }
     if (p.splits == 0) {
-        const uint64_t target = (uint64_t)std::max(num_cus, 1) * 8;
+        const uint64_t target = (uint64_t)std::max(num_cus, 1) * per_cu;
         uint64_t s = (target + units - 1) / std::max<uint64_t>(units, 1);
         s = std::min<uint64_t>(s, std::max<uint64_t>(nwords / 2, 1));  // >= 64 buckets per split
         const uint64_t per_split = (uint64_t)g.B * g.stride;

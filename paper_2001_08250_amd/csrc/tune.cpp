@@ -99,18 +99,20 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
             }
         }
     }
-    for (uint32_t t : {16u, 32u, 64u}) {
-        if (t > 2 * B)
-            continue;
-        Plan base = resolve_plan(g, Plan{KIND_M4R, t, 0, 0}, db->num_cus);
-        for (uint32_t sm : {1u, 2u, 4u}) {
-            Plan a = base, b = base;
-            a.splits = std::max<uint32_t>(1, base.splits / sm);
-            b.splits = base.splits * sm;
-            if (plan_supported(a))
-                cands.push_back(a);
-            if (sm > 1 && plan_supported(b))
-                cands.push_back(b);
+    for (uint32_t nw : {4u, 8u, 16u}) {
+        for (uint32_t t : {16u, 32u, 64u}) {
+            if (t * nw > 4 * B && !(t == 16 && nw == 4))
+                continue;
+            Plan base = resolve_plan(g, Plan{KIND_M4R, t, 0, nw}, db->num_cus);
+            for (uint32_t sm : {1u, 2u}) {
+                Plan a = base, b = base;
+                a.splits = std::max<uint32_t>(1, base.splits / sm);
+                b.splits = base.splits * sm;
+                if (plan_supported(a))
+                    cands.push_back(a);
+                if (sm > 1 && plan_supported(b))
+                    cands.push_back(b);
+            }
         }
     }
     hipEvent_t e0, e1;

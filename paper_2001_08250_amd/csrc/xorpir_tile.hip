@@ -79,7 +79,11 @@ __device__ __forceinline__ void apply_bucket(uint4 (&acc)[T], const uint4 v, con
 }
 
 // Accumulate buckets [jb, je) (jb a multiple of 32) of column `colc` for the
-// T request rows starting at r0 into acc. Rows >= B contribute nothing.
+// T request rows starting at r0 into acc. Rows >= B contribute nothing. One
+// loop iteration consumes one 32-bit request word; its 32 buckets are fully
+// unrolled so every bit test has a constant position (one s_bfe_i32 for the
+// mask, or one s_bitcmp1 + branch for the zero-skip). Loads of D run U
+// buckets ahead, across word boundaries, with rows clamped to the range end.
 template <int T, int KIND, int U>
 __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__restrict__ D, uint32_t stride16,
                                                 uint64_t n, const uint32_t *__restrict__ Q, uint64_t qpitch_w,
@@ -98,33 +102,28 @@ __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__
     for (int u = 0; u < U; ++u)
         nxt[u] = Dc[std::min<uint64_t>(jb + u, last) * stride16];
 
-    uint32_t qw[T];
+    for (uint64_t j = jb; j < je; j += 32) {
+        const uint64_t w = j >> 5;
+        uint32_t valid = ~0u;
+        if (((w + 1) << 5) > n)
+            valid = (1u << (n & 31u)) - 1u;
+        uint32_t qw[T];
 #pragma unroll
-    for (int r = 0; r < T; ++r)
-        qw[r] = 0u;
-    for (uint64_t j = jb; j < je; j += U) {
-        if ((j & 31u) == 0) {
-            const uint64_t w = j >> 5;
-            uint32_t valid = ~0u;
-            if (((w + 1) << 5) > n)
-                valid = (1u << (n & 31u)) - 1u;
+        for (int r = 0; r < T; ++r)
+            qw[r] = (r0 + r < B) ? (Q[(uint64_t)(r0 + r) * qpitch_w + w] & valid) : 0u;
 #pragma unroll
-            for (int r = 0; r < T; ++r)
-                qw[r] = (r0 + r < B) ? (Q[(uint64_t)(r0 + r) * qpitch_w + w] & valid) : 0u;
-        }
-        uint4 cur[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            cur[u] = nxt[u];
-        if (j + U < je) {
+        for (int c = 0; c < 32; c += U) {
+            uint4 cur[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                nxt[u] = Dc[std::min<uint64_t>(j + U + u, last) * stride16];
-        }
-        const int b0 = (int)(j & 31u);
+                cur[u] = nxt[u];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            apply_bucket<T, KIND>(acc, cur[u], qw, b0 + u);
+            for (int u = 0; u < U; ++u)
+                nxt[u] = Dc[std::min<uint64_t>(j + c + U + u, last) * stride16];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                apply_bucket<T, KIND>(acc, cur[u], qw, c + u);
+        }
     }
 }
 
@@ -326,6 +325,19 @@ hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream)
 
 bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
 
+hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                             uint64_t out_pitch, hipStream_t stream)
+{
+    const uint32_t stride16 = (uint32_t)(stride / 16);
+    const uint64_t count = (uint64_t)B * stride16;
+    if (count == 0)
+        return hipSuccess;
+    const uint32_t rgrid = (uint32_t)((count + WG - 1) / WG);
+    hipLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream, static_cast<const uint4 *>(partials),
+                       count, splits, count, stride16, static_cast<uint4 *>(out), out_pitch / 16);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
 {
     TileFn fn = tile_fn(p);
@@ -359,12 +371,7 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.splits <= 1)
         return e;
-    const uint64_t count = (uint64_t)g.B * a.stride16;
-    const uint32_t rgrid = (uint32_t)((count + WG - 1) / WG);
-    hipLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream,
-                       static_cast<const uint4 *>(partials), a.out_split16, p.splits, count, a.stride16,
-                       static_cast<uint4 *>(g.out), g.out_pitch / 16);
-    return hipGetLastError();
+    return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);
 }
 
 }  // namespace talek

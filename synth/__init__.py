@@ -126,6 +126,12 @@ def write_ops(seed: int, count: int, n: int, z: int, id_offset_seed: int | None 
     return ids, b1, b2, payload
 
 
+def uniform_indices(seed: int, count: int, n: int) -> np.ndarray:
+    """count indices uniform in [0, n) (uint64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n, size=count, dtype=np.uint64)
+
+
 def batch_sizes(seed: int, count: int, lo: int = 1, hi: int = 1024) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(lo, hi + 1, size=count).astype(np.uint32)

@@ -49,6 +49,49 @@ def test_small_workload_every_tile_schedule(kind):
                     assert_rows_equal(db.read(req37), want37, f"B=37 kind={kind} T={t} U={u} S={s}")
 
 
+M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
+
+
+def test_four_russians_every_shape():
+    """Four-Russians kernel: every (waves, requests/wave) shape, splits, ragged B."""
+    n, d, z = 1024, 4, 1024
+    D = synth.uniform_db(1001, n, d * z)
+    reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300)}
+    wants = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
+    with _db(D, d, z) as db:
+        for nw, tw in M4R_SHAPES:
+            for sp in (1, 0, 7):
+                db.set_plan(pir.KERNEL_M4R, tw, sp, nw)
+                for B, r in reqs.items():
+                    say(f"m4r nw={nw} tw={tw} splits={sp} B={B}")
+                    assert_rows_equal(db.read(r), wants[B], f"m4r nw={nw} tw={tw} S={sp} B={B}")
+
+
+@pytest.mark.parametrize("n,d,z,B", [(37, 3, 20, 5), (1000, 1, 8, 70), (333, 2, 520, 17), (4097, 4, 1024, 133),
+                                     (300, 2, 4096, 66), (2049, 8, 40, 2), (71, 1, 4, 9)])
+def test_four_russians_ragged_shapes(n, d, z, B):
+    D = synth.uniform_db(n * 11 + d, n, d * z)
+    req = synth.bernoulli_requests(n + 3 * B, B, n)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        for nw, tw in ((4, 32), (8, 16), (16, 32)):
+            db.set_plan(pir.KERNEL_M4R, tw, 0, nw)
+            assert_rows_equal(db.read(req), want, f"m4r nw={nw} tw={tw}")
+
+
+def test_four_russians_one_hot_and_densities():
+    n, d, z = 1000, 2, 64
+    D = synth.uniform_db(35, n, d * z)
+    idx = [0, 1, 7, 8, 31, 32, 33, 63, 64, 255, 256, 511, 512, 991, 992, 998, 999]
+    onehot = synth.bits_to_rows(np.eye(n, dtype=bool)[idx])
+    with _db(D, d, z) as db:
+        db.set_plan(pir.KERNEL_M4R, 16, 0, 8)
+        assert_rows_equal(db.read(onehot), D[idx], "m4r one-hot")
+        for p in (0.0, 0.01, 0.99, 1.0):
+            req = synth.bernoulli_requests(36, 70, n, p=p)
+            assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"m4r p={p}")
+
+
 @pytest.mark.parametrize("p", [0.0, 0.01, 0.5, 0.99, 1.0])
 def test_request_densities(p):
     n, d, z = 777, 4, 256
