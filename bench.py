@@ -44,12 +44,82 @@ def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
     return bits.sum(axis=1, dtype=np.int64)
 
 
+def serve_bench(args, pir):
+    """Serving workload: open-loop Poisson reads with 10% writes published every epoch."""
+    import torch  # noqa: F401  (device already selected by the caller)
+    w = configs.C5
+    x = w.extra
+    dur = args.duration
+    t = time.perf_counter()
+    db = pir.PirDB(w.n, w.d, w.z)
+    db.interest_config(x["interest_bits"], x["window"])
+    pre = synth.write_ops(w.cuckoo_seed, w.cuckoo_items, w.n, w.z)
+    ck = pir.Cuckoo(db, capacity=w.cuckoo_items, seed=w.cuckoo_seed, max_kicks=configs.CUCKOO_MAX_KICKS)
+    ck.insert_many(*pre)
+    ck.stage()
+    db.commit()
+    del pre
+    log(f"[serve] {w.name}: database of {w.db_bytes >> 30} GiB ready in {time.perf_counter() - t:.1f}s")
+    pool = synth.bernoulli_requests(w.req_seed, 1024, w.n)
+    results = []
+    for rate in [r for r in x["rates"] if not args.rates or r in args.rates]:
+        read_t = synth.poisson_arrivals(x["arrival_seed"] + rate, rate, dur)
+        rows = synth.uniform_indices(x["arrival_seed"] + rate + 1, read_t.size, 1024).astype(np.uint32)
+        write_t = synth.poisson_arrivals(x["arrival_seed"] + rate + 2, x["write_frac"] * rate, dur)
+        writes = synth.write_ops(w.cuckoo_seed + rate, write_t.size, w.n, w.z,
+                                 id_offset_seed=w.cuckoo_seed + rate + 3)
+        ipos = synth.interest_positions(x["arrival_seed"] + rate + 4, write_t.size, x["interest_k"],
+                                        x["interest_bits"])
+        row = {"rate": rate, "reads": int(read_t.size), "writes": int(write_t.size)}
+        for mode, mb, lanes in (("batched", args.max_batch, 2), ("one_per_read", 1, 4)):
+            if mode == "one_per_read" and args.no_baseline:
+                continue
+            # the one-launch-per-read baseline is given a shorter slice of the same trace
+            n_r = read_t.size if mode == "batched" else int(np.searchsorted(read_t, min(dur, args.baseline_s)))
+            n_w = int(np.searchsorted(write_t, read_t[n_r - 1])) if n_r else 0
+            log(f"[serve] rate {rate}/s {mode}: {n_r} reads, {n_w} writes")
+            out = pir.serve(db, ck, read_t=read_t[:n_r], read_row=rows[:n_r], req_pool=pool,
+                            write_t=write_t[:n_w], writes=tuple(a[:n_w] for a in writes),
+                            write_interest=ipos[:n_w], max_batch=mb, lanes=lanes, epoch_s=x["epoch_s"])
+            row[mode] = {"reads_per_s": round(out["reads_per_s"], 1), "p50_ms": round(1e3 * out["p50_s"], 3),
+                         "p99_ms": round(1e3 * out["p99_s"], 3), "max_ms": round(1e3 * out["max_s"], 3),
+                         "mean_batch": round(out["mean_batch"], 1), "batches": int(out["batches"]),
+                         "epochs": int(out["epochs"]), "wall_s": round(out["wall_s"], 3)}
+            log(f"[serve]   {row[mode]}")
+        results.append(row)
+    db.close()
+    best = max(results, key=lambda r: r["batched"]["reads_per_s"])
+    line = {
+        "metric": "PIR bucket-reads/sec at stated p99 (serving)",
+        "value": best["batched"]["reads_per_s"],
+        "unit": "reads/s",
+        "n_gpus": 1,
+        "steps": len(results),
+        "warmup": 0,
+        "ms_per_step": round(1e3 * dur, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z,
+                   "duration_s": dur, "max_batch": args.max_batch, "parallelism": "single-gpu"},
+        "serving": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4a", "c4b", "c3b"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4a", "c4b", "c3b", "c5"])
+    ap.add_argument("--duration", type=float, default=3.0, help="serving: seconds of arrivals per rate")
+    ap.add_argument("--baseline-s", type=float, default=1.0, help="serving: seconds of the one-per-read baseline")
+    ap.add_argument("--max-batch", type=int, default=1024, help="serving: reads per launch")
+    ap.add_argument("--rates", type=int, nargs="*", default=[], help="serving: subset of the arrival rates")
+    ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--step", default="", choices=["", "full", "read"],
                     help="full = writes + commit + read + interest fetch (default for cuckoo workloads)")
     ap.add_argument("--B", type=int, default=0, help="override the batch size")
@@ -57,8 +127,11 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=0, help="plan flags (1 = waves share a column chunk)")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-rows", type=int, default=256)
     args = ap.parse_args()
 
@@ -71,6 +144,8 @@ def main():
     import paper_2001_08250_amd as pir
 
     torch.cuda.set_device(0)
+    if args.workload == "c5":
+        return serve_bench(args, pir)
     w = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B, "c3b": configs.C3}[args.workload]
     B = args.B or w.B or 1024
     full = (args.step or ("full" if w.fill == "cuckoo" else "read")) == "full"
@@ -108,7 +183,7 @@ def main():
 
     req = synth.bernoulli_requests(w.req_seed, B, w.n)
     if args.kind:
-        db.set_plan(args.kind, args.tile, args.splits, args.unroll)
+        db.set_plan(args.kind, args.tile, args.splits, args.unroll, args.flags)
     if args.tune:
         p, us = db.tune(B, iters=3)
         log(f"[bench] tuned: {p} {us:.1f} us")
@@ -145,6 +220,13 @@ def main():
         if full:
             L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), sh)
 
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                      # read and write calib_copy_mib MiB each
+        torch.cuda.synchronize()
+        del src, dst
     for k in range(W):
         step(k)
     torch.cuda.synchronize()
@@ -228,7 +310,8 @@ def main():
         "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "B": B,
                    "step": "writes+commit+read+interest" if full else "read",
                    "writes_per_step": nw,
-                   "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll},
+                   "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll,
+                            "flags": plan.flags},
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,

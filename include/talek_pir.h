@@ -157,16 +157,25 @@ enum pir_kernel_kind {
     PIR_KERNEL_AUTO = 0,   /* tuning table, else the built-in heuristic */
     PIR_KERNEL_MASK = 1,   /* branch-free masked XOR (one 3-input op per word) */
     PIR_KERNEL_SKIP = 2,   /* wave-uniform zero-skip of unselected buckets */
-    PIR_KERNEL_M4R = 3     /* Four-Russians: XOR-combination tables in LDS */
+    PIR_KERNEL_M4R = 3,    /* Four-Russians: 8-bucket tables in LDS, 4 bytes per lane */
+    PIR_KERNEL_M4R_WIDE = 4 /* Four-Russians: 6-bucket tables in LDS, 16 bytes per lane */
 };
 
-/* A read schedule: kernel family, requests per wave tile, bucket splits
- * (0 = heuristic), unroll depth (0 = default). */
+/* Plan flags. SHARED_COLUMN (MASK and SKIP families): the four waves of a
+ * workgroup stream the same 1 KiB column chunk of D and take four
+ * consecutive request tiles, so the chunk is read from L2 once per
+ * workgroup instead of once per wave. */
+enum { PIR_PLAN_SHARED_COLUMN = 1 };
+
+/* A read schedule: kernel family, request tile (requests per wave), bucket
+ * splits (0 = heuristic), unroll (MASK/SKIP: buckets loaded ahead; M4R:
+ * waves per workgroup; 0 = default), flags. */
 typedef struct pir_plan {
     int32_t kind;
     uint32_t tile;
     uint32_t splits;
     uint32_t unroll;
+    uint32_t flags;
 } pir_plan;
 
 /* Force a schedule for subsequent reads of this handle (kind AUTO restores

@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libtalek_pir.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "talek_pir.h")
 
 PIR_OK, PIR_EINVAL, PIR_ERANGE, PIR_ENOMEM, PIR_EDEVICE, PIR_EFULL, PIR_EBUSY = 0, -1, -2, -3, -4, -5, -6
-KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R, KERNEL_M4R_WIDE = 0, 1, 2, 3, 4
+PLAN_SHARED_COLUMN = 1
 
 
 class PirError(RuntimeError):
@@ -34,10 +35,11 @@ class PirError(RuntimeError):
 
 class pir_plan(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("tile", ctypes.c_uint32), ("splits", ctypes.c_uint32),
-                ("unroll", ctypes.c_uint32)]
+                ("unroll", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
     def __repr__(self):
-        return f"pir_plan(kind={self.kind}, tile={self.tile}, splits={self.splits}, unroll={self.unroll})"
+        return (f"pir_plan(kind={self.kind}, tile={self.tile}, splits={self.splits}, unroll={self.unroll}, "
+                f"flags={self.flags})")
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -261,8 +263,8 @@ class PirDB:
             None if of is None else _ptr(of, ctypes.c_uint64), _stream_handle(stream)), "pir_read_stream_async")
 
     # schedule ---------------------------------------------------------------
-    def set_plan(self, kind=KERNEL_AUTO, tile=0, splits=0, unroll=0):
-        p = pir_plan(kind, tile, splits, unroll)
+    def set_plan(self, kind=KERNEL_AUTO, tile=0, splits=0, unroll=0, flags=0):
+        p = pir_plan(kind, tile, splits, unroll, flags)
         _check(self._L.pir_set_plan(self.h, ctypes.byref(p)), "pir_set_plan")
 
     def get_plan(self, B: int) -> pir_plan:

@@ -16,6 +16,7 @@ ARCH = os.environ.get("TALEK_OFFLOAD_ARCH", "gfx950")
 SOURCES = [
     "xorpir_tile.hip",
     "xorpir_m4r.hip",
+    "xorpir_m4rw.hip",
     "aux_kernels.hip",
     "plan.cpp",
     "pir_db.cpp",

@@ -48,6 +48,7 @@ struct pir_db {
     uint64_t stride = 0;        // bucket_bytes rounded up to 16
     uint64_t qbytes = 0;        // ceil(n / 8)
     uint64_t qpitch = 0;        // internal request pitch (multiple of 16)
+    uint64_t rows_alloc = 0;    // device rows per snapshot copy (n plus zero padding)
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;  // graph capture only, never executes
 
@@ -77,7 +78,7 @@ struct pir_db {
     bool all_dirty = false;
 
     std::unordered_map<hipStream_t, talek::Scratch> scratch;
-    talek::Plan forced{0, 0, 0, 0};
+    talek::Plan forced{0, 0, 0, 0, 0};
 
     // interest vector
     uint64_t m_bits = 0;

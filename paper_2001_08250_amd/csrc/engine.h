@@ -8,10 +8,17 @@
 namespace talek {
 
 // Kernel families (values match enum pir_kernel_kind).
-enum Kind : int { KIND_AUTO = 0, KIND_MASK = 1, KIND_SKIP = 2, KIND_M4R = 3 };
+enum Kind : int { KIND_AUTO = 0, KIND_MASK = 1, KIND_SKIP = 2, KIND_M4R = 3, KIND_M4RW = 4 };
+
+// Rows allocated for a database of n buckets: n rounded up to 32 plus 64
+// more, all zero beyond n. Kernels may read (never use) any row below this,
+// which lets them stream whole 32-bucket request words and prefetch past the
+// end of their range without per-row clamping.
+inline uint64_t padded_db_rows(uint64_t n) { return ((n + 31) & ~31ull) + 64; }
 
 // Geometry of one read launch. D rows are `stride` bytes apart (stride is
-// bucket_bytes rounded up to 16; padding bytes are zero). Request rows are
+// bucket_bytes rounded up to 16; padding bytes are zero) and
+// padded_db_rows(n) rows are readable. Request rows are
 // `qpitch` bytes apart, qpitch % 4 == 0, each row readable up to
 // round_up(ceil(n/8), 4) bytes. Output rows are `out_pitch` bytes apart,
 // out_pitch % 16 == 0, and receive `stride` bytes each.
@@ -30,8 +37,10 @@ struct Plan {
     int kind;
     uint32_t tile;     // requests per wave
     uint32_t splits;   // bucket-range splits (1 = none)
-    uint32_t unroll;   // buckets loaded ahead
+    uint32_t unroll;   // buckets loaded ahead (M4R: waves per workgroup)
+    uint32_t flags;    // PLAN_SHARED_COLUMN
 };
+constexpr uint32_t PLAN_SHARED_COLUMN = 1;
 
 // Device scratch the read needs for split partials: bytes.
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p);

@@ -108,7 +108,7 @@ int ensure_back(pir_db *db)
 {
     if (db->have_back)
         return PIR_OK;
-    const uint64_t bytes = db->n * db->stride;
+    const uint64_t bytes = db->rows_alloc * db->stride;
     if (!db->buf[db->front ^ 1]) {
         void *p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -297,7 +297,7 @@ int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
     if (bucket > (1ull << 30) || n > (1ull << 40))
         return PIR_EINVAL;
     const uint64_t stride = (bucket + 15) & ~15ull;
-    if (stride / 16 > 0xffffffffull || n > UINT64_MAX / stride)
+    if (stride / 16 > 0xffffffffull || n + 128 > UINT64_MAX / stride)
         return PIR_EINVAL;
     pir_db *db = new (std::nothrow) pir_db();
     if (!db)
@@ -327,9 +327,13 @@ int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
         if (rc != PIR_OK)
             break;
         void *p = nullptr;
-        if (hipMalloc(&p, n * stride) != hipSuccess) { rc = PIR_ENOMEM; break; }
+        db->rows_alloc = talek::padded_db_rows(n);
+        if (hipMalloc(&p, db->rows_alloc * stride) != hipSuccess) { rc = PIR_ENOMEM; break; }
         db->buf[0] = static_cast<uint8_t *>(p);
-        if (launch_fill_zero(db->buf[0], n * stride, db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
+        if (launch_fill_zero(db->buf[0], db->rows_alloc * stride, db->stream) != hipSuccess) {
+            rc = PIR_EDEVICE;
+            break;
+        }
         db->stage_cap = std::max<uint64_t>(1, std::min<uint64_t>(n, STAGE_BYTES / stride));
         if (hipHostMalloc(&p, db->stage_cap * stride, hipHostMallocDefault) != hipSuccess) { rc = PIR_ENOMEM; break; }
         db->stage_host = static_cast<uint8_t *>(p);
@@ -586,8 +590,8 @@ int pir_set_plan(pir_db *db, const pir_plan *plan)
 {
     if (!db || !plan)
         return PIR_EINVAL;
-    Plan p{plan->kind, plan->tile, plan->splits, plan->unroll};
-    if (p.kind < KIND_AUTO || p.kind > KIND_M4R)
+    Plan p{plan->kind, plan->tile, plan->splits, plan->unroll, plan->flags};
+    if (p.kind < KIND_AUTO || p.kind > KIND_M4RW)
         return PIR_EINVAL;
     if (p.kind != KIND_AUTO) {
         ReadGeom g = read_geom(db, nullptr, db->qpitch, std::max<uint32_t>(p.tile, 1), nullptr, db->stride);
@@ -610,6 +614,7 @@ int pir_get_plan(pir_db *db, uint32_t B, pir_plan *plan)
     plan->tile = p.tile;
     plan->splits = p.splits;
     plan->unroll = p.unroll;
+    plan->flags = p.flags;
     return PIR_OK;
 }
 

@@ -11,6 +11,11 @@ bool m4r_plan_supported(const Plan &p);
 hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
 uint32_t m4r_tasks(const ReadGeom &g, const Plan &p);
 uint64_t m4r_staging_bytes(const ReadGeom &g);
+bool m4rw_plan_supported(const Plan &p);
+hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p);
+uint64_t m4rw_staging_bytes(const ReadGeom &g);
+uint64_t m4rw_groups(uint64_t n);
 
 namespace {
 
@@ -30,6 +35,8 @@ bool plan_supported(const Plan &p)
 {
     if (p.kind == KIND_M4R)
         return m4r_plan_supported(p);
+    if (p.kind == KIND_M4RW)
+        return m4rw_plan_supported(p);
     return tile_plan_supported(p);
 }
 
@@ -38,6 +45,8 @@ uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
     uint64_t bytes = p.splits <= 1 ? 0 : (uint64_t)p.splits * g.B * g.stride;
     if (p.kind == KIND_M4R)
         bytes += m4r_staging_bytes(g);
+    if (p.kind == KIND_M4RW)
+        bytes += m4rw_staging_bytes(g);
     return bytes;
 }
 
@@ -45,7 +54,7 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
     if (p.kind == KIND_AUTO)
-        p.kind = g.B >= 64 ? KIND_M4R : KIND_MASK;
+        p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
     const uint64_t nwords = (g.n + 31) / 32;
     const uint32_t stride16 = (uint32_t)(g.stride / 16);
     uint64_t units;  // independent workgroup tasks per split
@@ -56,15 +65,24 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
             p.tile = 32;
         if (p.unroll == 0)
             p.unroll = g.B >= 256 ? 8 : 4;
-        units = m4r_tasks(g, Plan{p.kind, p.tile, 1, p.unroll});
+        units = m4r_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
         per_cu = 2;  // one 128 KiB LDS table pair per CU at a time
+    } else if (p.kind == KIND_M4RW) {
+        if (p.tile == 0)
+            p.tile = g.B > 128 ? 32 : 16;
+        if (p.unroll == 0)
+            p.unroll = 8;
+        units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
+        per_cu = 2;
     } else {
         if (p.tile == 0)
             p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;
         if (p.unroll == 0)
-            p.unroll = p.tile <= 2 ? 16 : 8;
-        const uint64_t n_rt = (g.B + p.tile - 1) / p.tile;
-        const uint64_t n_cg = (stride16 + 255) / 256;
+            p.unroll = p.tile <= 2 ? 16 : p.tile >= 16 ? 4 : 8;
+        const bool share = p.flags & PLAN_SHARED_COLUMN;
+        const uint64_t rows_per_wg = (uint64_t)p.tile * (share ? 4 : 1);
+        const uint64_t n_rt = (g.B + rows_per_wg - 1) / rows_per_wg;
+        const uint64_t n_cg = share ? (stride16 + 63) / 64 : (stride16 + 255) / 256;
         units = n_rt * n_cg;
     }
     if (p.splits == 0) {
@@ -76,7 +94,8 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
             s = std::min<uint64_t>(s, std::max<uint64_t>(PARTIAL_CAP / per_split, 1));
         p.splits = (uint32_t)std::max<uint64_t>(s, 1);
     }
-    p.splits = (uint32_t)std::min<uint64_t>(p.splits, std::max<uint64_t>(nwords, 1));
+    const uint64_t max_splits = p.kind == KIND_M4RW ? m4rw_groups(g.n) : nwords;
+    p.splits = (uint32_t)std::min<uint64_t>(p.splits, std::max<uint64_t>(max_splits, 1));
     return p;
 }
 
@@ -86,6 +105,8 @@ hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStre
         return hipSuccess;
     if (p.kind == KIND_M4R)
         return launch_m4r_read(g, p, partials, stream);
+    if (p.kind == KIND_M4RW)
+        return launch_m4rw_read(g, p, partials, stream);
     return launch_tile_read(g, p, partials, stream);
 }
 

@@ -84,8 +84,9 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
         for (uint32_t t : tiles) {
             if (t > 2 * B && t != 1)
                 continue;
-            for (uint32_t u : {4u, 8u, 16u}) {
-                Plan base = resolve_plan(g, Plan{kind, t, 0, u}, db->num_cus);
+            for (uint32_t u : {4u, 8u, 16u})
+            for (uint32_t fl : {0u, PLAN_SHARED_COLUMN}) {
+                Plan base = resolve_plan(g, Plan{kind, t, 0, u, fl}, db->num_cus);
                 for (uint32_t sm : {1u, 2u, 4u}) {
                     for (int dir = 0; dir < 2; ++dir) {
                         if (sm == 1 && dir == 1)
@@ -103,7 +104,21 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
         for (uint32_t t : {16u, 32u, 64u}) {
             if (t * nw > 4 * B && !(t == 16 && nw == 4))
                 continue;
-            Plan base = resolve_plan(g, Plan{KIND_M4R, t, 0, nw}, db->num_cus);
+            Plan base = resolve_plan(g, Plan{KIND_M4R, t, 0, nw, 0}, db->num_cus);
+            for (uint32_t sm : {1u, 2u}) {
+                Plan a = base, b = base;
+                a.splits = std::max<uint32_t>(1, base.splits / sm);
+                b.splits = base.splits * sm;
+                if (plan_supported(a))
+                    cands.push_back(a);
+                if (sm > 1 && plan_supported(b))
+                    cands.push_back(b);
+            }
+        }
+    }
+    for (uint32_t nw : {4u, 8u, 16u}) {
+        for (uint32_t t : {16u, 32u}) {
+            Plan base = resolve_plan(g, Plan{KIND_M4RW, t, 0, nw, 0}, db->num_cus);
             for (uint32_t sm : {1u, 2u}) {
                 Plan a = base, b = base;
                 a.splits = std::max<uint32_t>(1, base.splits / sm);
@@ -155,6 +170,7 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
         best->tile = win.tile;
         best->splits = win.splits;
         best->unroll = win.unroll;
+        best->flags = win.flags;
     }
     if (best_us)
         *best_us = win_us;
@@ -175,9 +191,9 @@ int pir_tune_save(const char *path)
         const Plan &p = kv.second.plan;
         fprintf(f,
                 "  {\"n\": %llu, \"bclass\": %u, \"stride\": %llu, \"kind\": %d, \"tile\": %u, \"splits\": %u, "
-                "\"unroll\": %u, \"us\": %.3f}%s\n",
+                "\"unroll\": %u, \"flags\": %u, \"us\": %.3f}%s\n",
                 (unsigned long long)std::get<0>(kv.first), std::get<1>(kv.first),
-                (unsigned long long)std::get<2>(kv.first), p.kind, p.tile, p.splits, p.unroll, kv.second.us,
+                (unsigned long long)std::get<2>(kv.first), p.kind, p.tile, p.splits, p.unroll, p.flags, kv.second.us,
                 ++i < g_table.size() ? "," : "");
     }
     fprintf(f, "]}\n");
@@ -199,18 +215,18 @@ int pir_tune_load(const char *path)
         if (!strstr(line, "\"bclass\""))
             continue;
         unsigned long long n = 0, stride = 0;
-        unsigned bclass = 0, tile = 0, splits = 0, unroll = 0;
+        unsigned bclass = 0, tile = 0, splits = 0, unroll = 0, flags = 0;
         int kind = 0;
         double us = 0;
         const int got = sscanf(line,
                                " {\"n\": %llu, \"bclass\": %u, \"stride\": %llu, \"kind\": %d, \"tile\": %u, "
-                               "\"splits\": %u, \"unroll\": %u, \"us\": %lf",
-                               &n, &bclass, &stride, &kind, &tile, &splits, &unroll, &us);
-        if (got != 8 || kind < KIND_MASK || kind > KIND_M4R) {
+                               "\"splits\": %u, \"unroll\": %u, \"flags\": %u, \"us\": %lf",
+                               &n, &bclass, &stride, &kind, &tile, &splits, &unroll, &flags, &us);
+        if (got != 9 || kind < KIND_MASK || kind > KIND_M4RW) {
             rc = PIR_EINVAL;
             continue;
         }
-        Plan p{kind, tile, splits, unroll};
+        Plan p{kind, tile, splits, unroll, flags};
         if (!plan_supported(p)) {
             rc = PIR_EINVAL;
             continue;

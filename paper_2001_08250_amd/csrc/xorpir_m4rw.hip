@@ -1,0 +1,302 @@
+// Four-Russians XOR-PIR kernel with 16-byte table entries per lane (gfx950).
+//
+// Same method as xorpir_m4r.hip (Arlazarov, Dinic, Kronrod, Faradzev 1970):
+// buckets are taken 6 at a time, the workgroup builds the 64 XOR
+// combinations of a group once, and every request adds the combination its 6
+// request bits select. Here each lane owns 16 bytes of the bucket row, so a
+// table entry is a 1 KiB row slice and a lookup is one ds_read_b128: on
+// gfx950 128-bit LDS reads deliver about twice the bytes per clock of 32-bit
+// reads, and LDS bandwidth is what bounds this kernel. A group table is
+// 64 entries x 1 KiB = 64 KiB; two of them (double buffering: build group
+// x + 1 while looking up group x, one barrier per group) fill 128 KiB of LDS.
+//
+// Per request and group of 6 buckets: one v_add_u32 (LDS address from a
+// pre-scaled, wave-uniform offset), one ds_read_b128 and four v_xor_b32 for
+// 24 (bucket, dword) terms. The table costs 63 x 4 XORs and 64 ds_write_b128
+// per group, split over the workgroup's waves and shared by all its requests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "engine.h"
+
+namespace talek {
+
+hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                             uint64_t out_pitch, hipStream_t stream);
+
+namespace {
+
+constexpr int GB = 6;                        // buckets per group
+constexpr int ENTRIES = 1 << GB;             // 64
+constexpr int ENTRY_BYTES = 64 * 16;         // one 1 KiB row slice
+constexpr int TABLE_U4 = ENTRIES * 64;       // uint4 per table buffer
+
+struct WideArgs {
+    const uint8_t *D;
+    uint64_t row_bytes;     // stride
+    uint32_t slices;        // 1 KiB column slices per row
+    uint32_t stride16;
+    uint32_t B;
+    uint32_t Bp;            // staged rows per group (multiple of 64)
+    const uint32_t *Qs;     // Qs[g * Bp + r] = (6 request bits of group g) * ENTRY_BYTES
+    uint32_t *out;          // uint4 rows via out_row16 / out_split16
+    uint64_t out_row16;
+    uint64_t out_split16;
+    uint64_t groups;        // ceil(n / 6)
+    uint32_t n_rt, splits, groups_per_split, tasks_per_xcd;
+};
+
+template <int NW>
+constexpr int log2_waves()
+{
+    return NW == 1 ? 0 : NW == 2 ? 1 : NW == 4 ? 2 : NW == 8 ? 3 : 4;
+}
+
+// The 6 bucket row slices of group g for this lane (the database has
+// padded_db_rows(n) readable rows; rows past n only meet zero request bits).
+__device__ __forceinline__ void load_group(uint4 (&d)[GB], const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                           uint32_t lane_off, uint64_t g)
+{
+    const uint8_t *row = D + g * GB * row_bytes;
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+        d[i] = *reinterpret_cast<const uint4 *>(row + lane_off);
+        row += row_bytes;
+    }
+}
+
+__device__ __forceinline__ void xor4(uint4 &a, const uint4 &b)
+{
+    a.x ^= b.x;
+    a.y ^= b.y;
+    a.z ^= b.z;
+    a.w ^= b.w;
+}
+
+// Wave w writes entries (w << LB) | x, x < 2^LB, walking x in Gray code
+// order: one 4-dword XOR and one ds_write_b128 per entry.
+template <int NW>
+__device__ __forceinline__ void build_table(uint4 *__restrict__ tbl, const uint4 (&d)[GB], uint32_t wave,
+                                            uint32_t lane)
+{
+    constexpr int LW = log2_waves<NW>();
+    constexpr int LB = GB - LW;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int b = 0; b < LW; ++b)
+        if ((wave >> b) & 1u)
+            xor4(v, d[LB + b]);
+    uint4 *w = tbl + ((wave << LB) * 64u + lane);
+    w[0] = v;
+#pragma unroll
+    for (int k = 1; k < (1 << LB); ++k) {
+        xor4(v, d[__builtin_ctz(k)]);
+        w[(k ^ (k >> 1)) * 64] = v;
+    }
+}
+
+// Lookups in batches of 8: eight ds_read_b128 in flight per wave before the
+// first XOR, to cover the LDS latency.
+template <int TW>
+__device__ __forceinline__ void lookup(uint4 (&acc)[TW], const uint8_t *tbl, const uint32_t *__restrict__ off)
+{
+    constexpr int BATCH = TW < 8 ? TW : 8;
+#pragma unroll
+    for (int r0 = 0; r0 < TW; r0 += BATCH) {
+        uint4 t[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i)
+            t[i] = *reinterpret_cast<const uint4 *>(tbl + off[r0 + i]);
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i)
+            xor4(acc[r0 + i], t[i]);
+    }
+}
+
+// Group step for group x (K = parity of x - first group): refill ring[K]
+// (group x, already built) with group x + 2, build group x + 1 into the other
+// buffer, look up group x, synchronise. Loads and builds past the range are
+// harmless (readable padding rows, a table nobody reads) and keep the code
+// straight-line so the waits stay exact.
+template <int NW, int TW, int K>
+__device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[2][GB], uint4 *lds,
+                                           const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
+                                           uint64_t x, const uint32_t *__restrict__ q, bool active, uint32_t wave,
+                                           uint32_t lane)
+{
+    load_group(ring[K], D, row_bytes, lane_off, x + 2);
+    build_table<NW>(lds + (K ^ 1) * TABLE_U4, ring[K ^ 1], wave, lane);
+    if (active)
+        lookup<TW>(acc, reinterpret_cast<const uint8_t *>(lds + K * TABLE_U4 + lane), q);
+    __syncthreads();
+}
+
+template <int NW, int TW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, NW / 4)))
+void xorpir_m4rw_kernel(const WideArgs a)
+{
+    __shared__ uint4 lds[2 * TABLE_U4];
+    const uint32_t L = blockIdx.x;
+    const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
+    if (t >= a.n_rt * a.slices * a.splits)
+        return;
+    const uint32_t rt = t % a.n_rt;
+    const uint32_t rest = t / a.n_rt;
+    const uint32_t slice = rest % a.slices;
+    const uint32_t s = rest / a.slices;
+
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t col = slice * 64u + lane;
+    const bool col_ok = col < a.stride16;
+    const uint32_t lane_off = (col_ok ? col : slice * 64u) * 16u;
+    const uint32_t r0 = rt * (NW * TW) + wave * TW;
+    const bool active = r0 < a.B;
+
+    const uint64_t gb = (uint64_t)s * a.groups_per_split;
+    const uint64_t ge = std::min<uint64_t>(a.groups, gb + a.groups_per_split);
+
+    uint4 acc[TW];
+#pragma unroll
+    for (int r = 0; r < TW; ++r)
+        acc[r] = make_uint4(0u, 0u, 0u, 0u);
+
+    if (gb < ge) {
+        uint4 ring[2][GB];
+        load_group(ring[0], a.D, a.row_bytes, lane_off, gb);
+        load_group(ring[1], a.D, a.row_bytes, lane_off, gb + 1);
+        build_table<NW>(lds, ring[0], wave, lane);
+        __syncthreads();
+        const uint32_t *Qw = a.Qs + r0;
+        uint64_t x = gb;
+        for (; x + 2 <= ge; x += 2) {
+            group_step<NW, TW, 0>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw + x * a.Bp, active, wave, lane);
+            group_step<NW, TW, 1>(acc, ring, lds, a.D, a.row_bytes, lane_off, x + 1, Qw + (x + 1) * a.Bp, active,
+                                  wave, lane);
+        }
+        if (x < ge)
+            group_step<NW, TW, 0>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw + x * a.Bp, active, wave, lane);
+    }
+
+    if (active && col_ok) {
+        uint4 *o = reinterpret_cast<uint4 *>(a.out) + (uint64_t)s * a.out_split16 + col;
+#pragma unroll
+        for (int r = 0; r < TW; ++r)
+            if (r0 + r < a.B)
+                o[(uint64_t)(r0 + r) * a.out_row16] = acc[r];
+    }
+}
+
+// Qs[g * Bp + r] = (bits 6g .. 6g+5 of request row r, bits >= n cleared) *
+// ENTRY_BYTES; rows B <= r < Bp are zero. One thread per (group, row).
+__global__ __launch_bounds__(256) void stage_wide_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
+                                                                 uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
+                                                                 uint32_t Bp, uint64_t groups)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= groups * Bp)
+        return;
+    const uint64_t g = i / Bp;
+    const uint32_t r = (uint32_t)(i % Bp);
+    uint32_t v = 0;
+    if (r < B) {
+        const uint64_t nwords = (n + 31) >> 5;
+        const uint64_t bit = g * GB;
+        const uint64_t w = bit >> 5;
+        const uint32_t sh = (uint32_t)(bit & 31u);
+        const uint32_t *row = Q + (uint64_t)r * qpitch_w;
+        uint64_t win = row[w];
+        if (w + 1 < nwords)
+            win |= (uint64_t)row[w + 1] << 32;
+        v = (uint32_t)(win >> sh) & (ENTRIES - 1);
+        if (bit + GB > n) {
+            const uint64_t keep = n > bit ? n - bit : 0;
+            v &= (1u << keep) - 1u;
+        }
+    }
+    Qs[i] = v * ENTRY_BYTES;
+}
+
+using WideFn = void (*)(const WideArgs);
+
+WideFn wide_fn(uint32_t nw, uint32_t tw)
+{
+    if (nw == 4 && tw == 32) return xorpir_m4rw_kernel<4, 32>;
+    if (nw == 8 && tw == 16) return xorpir_m4rw_kernel<8, 16>;
+    if (nw == 8 && tw == 32) return xorpir_m4rw_kernel<8, 32>;
+    if (nw == 16 && tw == 16) return xorpir_m4rw_kernel<16, 16>;
+    return nullptr;
+}
+
+uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
+
+}  // namespace
+
+// Plan fields for this family: tile = requests per wave (TW), unroll = waves
+// per workgroup (NW).
+bool m4rw_plan_supported(const Plan &p) { return wide_fn(p.unroll, p.tile) != nullptr; }
+
+uint64_t m4rw_staging_bytes(const ReadGeom &g)
+{
+    const uint64_t groups = (g.n + GB - 1) / GB;
+    return (groups * padded_rows(g.B) * 4 + 255) & ~255ull;
+}
+
+uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
+{
+    const uint32_t stride16 = (uint32_t)(g.stride / 16);
+    const uint32_t slices = (stride16 + 63) / 64;
+    const uint32_t R = std::max<uint32_t>(1, p.tile * p.unroll);
+    return ((g.B + R - 1) / R) * slices;
+}
+
+uint64_t m4rw_groups(uint64_t n) { return (n + GB - 1) / GB; }
+
+hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+{
+    WideFn fn = wide_fn(p.unroll, p.tile);
+    if (!fn)
+        return hipErrorInvalidValue;
+    WideArgs a{};
+    a.D = static_cast<const uint8_t *>(g.D);
+    a.row_bytes = g.stride;
+    a.stride16 = (uint32_t)(g.stride / 16);
+    a.slices = (a.stride16 + 63) / 64;
+    a.B = g.B;
+    a.Bp = padded_rows(g.B);
+    a.groups = m4rw_groups(g.n);
+    uint32_t *qs = static_cast<uint32_t *>(partials);
+    {
+        const uint64_t threads = a.groups * a.Bp;
+        hipLaunchKernelGGL(stage_wide_offsets_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, stream,
+                           static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    a.Qs = qs;
+    partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g);
+    const uint32_t R = p.tile * p.unroll;
+    a.n_rt = (g.B + R - 1) / R;
+    a.splits = p.splits;
+    a.groups_per_split = (uint32_t)((a.groups + p.splits - 1) / p.splits);
+    if (p.splits > 1) {
+        a.out = static_cast<uint32_t *>(partials);
+        a.out_row16 = a.stride16;
+        a.out_split16 = (uint64_t)g.B * a.stride16;
+    } else {
+        a.out = static_cast<uint32_t *>(g.out);
+        a.out_row16 = g.out_pitch / 16;
+        a.out_split16 = 0;
+    }
+    const uint64_t tasks = (uint64_t)a.n_rt * a.slices * a.splits;
+    a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
+    hipLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || p.splits <= 1)
+        return e;
+    return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);
+}
+
+}  // namespace talek

@@ -83,7 +83,12 @@ __device__ __forceinline__ void apply_bucket(uint4 (&acc)[T], const uint4 v, con
 // loop iteration consumes one 32-bit request word; its 32 buckets are fully
 // unrolled so every bit test has a constant position (one s_bfe_i32 for the
 // mask, or one s_bitcmp1 + branch for the zero-skip). Loads of D run U
-// buckets ahead, across word boundaries, with rows clamped to the range end.
+// buckets ahead, across word boundaries; the database has
+// padded_db_rows(n) readable rows, so whole words and the prefetch past the
+// range end need no clamping (those rows only meet request bits that are
+// zero). The row address is wave-uniform (SGPRs, advanced by the stride)
+// and the lane adds a fixed byte offset, so each load is one
+// global_load_dwordx4 with saddr + voffset.
 template <int T, int KIND, int U>
 __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__restrict__ D, uint32_t stride16,
                                                 uint64_t n, const uint32_t *__restrict__ Q, uint64_t qpitch_w,
@@ -95,12 +100,15 @@ __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__
         acc[r] = make_uint4(0u, 0u, 0u, 0u);
     if (jb >= je)
         return;
-    const uint4 *Dc = D + colc;
-    const uint64_t last = je - 1;
+    const uint64_t row_bytes = (uint64_t)stride16 * 16u;
+    const uint32_t lane_off = colc * 16u;
+    const uint8_t *row = reinterpret_cast<const uint8_t *>(D) + jb * row_bytes;  // next row to load
     uint4 nxt[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        nxt[u] = Dc[std::min<uint64_t>(jb + u, last) * stride16];
+    for (int u = 0; u < U; ++u) {
+        nxt[u] = *reinterpret_cast<const uint4 *>(row + lane_off);
+        row += row_bytes;
+    }
 
     for (uint64_t j = jb; j < je; j += 32) {
         const uint64_t w = j >> 5;
@@ -118,8 +126,10 @@ __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__
             for (int u = 0; u < U; ++u)
                 cur[u] = nxt[u];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                nxt[u] = Dc[std::min<uint64_t>(j + c + U + u, last) * stride16];
+            for (int u = 0; u < U; ++u) {
+                nxt[u] = *reinterpret_cast<const uint4 *>(row + lane_off);
+                row += row_bytes;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 apply_bucket<T, KIND>(acc, cur[u], qw, c + u);
@@ -127,7 +137,12 @@ __device__ __forceinline__ void tile_accumulate(uint4 (&acc)[T], const uint4 *__
     }
 }
 
-template <int T, int KIND, int U>
+// SHARE = false: the 4 waves take 4 consecutive 1 KiB column chunks (one
+// 4 KiB column group) of the same T request rows.
+// SHARE = true: the 4 waves stream the same 1 KiB column chunk and take 4
+// consecutive request tiles, so the chunk is fetched from L2 once and the
+// other three waves hit in L1.
+template <int T, int KIND, int U, bool SHARE>
 __global__ __launch_bounds__(WG) void xorpir_tile_kernel(const TileArgs a)
 {
     const uint32_t L = blockIdx.x;
@@ -139,16 +154,16 @@ __global__ __launch_bounds__(WG) void xorpir_tile_kernel(const TileArgs a)
     const uint32_t cg = rest % a.n_cg;
     const uint32_t s = rest / a.n_cg;
 
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave_col = cg * COLS_PER_WG + wave * 64u;
-    if (wave_col >= a.stride16)
-        return;  // this wave's column chunk is past the row end
+    const uint32_t wave_col = SHARE ? cg * 64u : cg * COLS_PER_WG + wave * 64u;
+    const uint32_t r0 = SHARE ? (rt * 4u + wave) * T : rt * T;
+    if (wave_col >= a.stride16 || r0 >= a.B)
+        return;  // nothing for this wave (no barriers follow)
     const uint32_t col = wave_col + lane;
     const bool col_ok = col < a.stride16;
     const uint32_t colc = col_ok ? col : wave_col;
 
-    const uint32_t r0 = rt * T;
     const uint64_t nwords = (a.n + 31) >> 5;
     const uint64_t wb = (uint64_t)s * a.words_per_split;
     const uint64_t we = std::min<uint64_t>(nwords, wb + a.words_per_split);
@@ -278,38 +293,39 @@ __global__ __launch_bounds__(WG) void xor_splits_kernel(const uint4 *__restrict_
 
 using TileFn = void (*)(const TileArgs);
 
-template <int KIND, int U>
+template <int KIND, int U, bool SHARE>
 TileFn pick_tile(uint32_t T)
 {
     switch (T) {
-    case 1: return xorpir_tile_kernel<1, KIND, U>;
-    case 2: return xorpir_tile_kernel<2, KIND, U>;
-    case 4: return xorpir_tile_kernel<4, KIND, U>;
-    case 8: return xorpir_tile_kernel<8, KIND, U>;
-    case 16: return xorpir_tile_kernel<16, KIND, U>;
-    case 24: return xorpir_tile_kernel<24, KIND, U>;
-    case 32: return xorpir_tile_kernel<32, KIND, U>;
+    case 1: return SHARE ? nullptr : xorpir_tile_kernel<1, KIND, U, false>;
+    case 2: return SHARE ? nullptr : xorpir_tile_kernel<2, KIND, U, false>;
+    case 4: return xorpir_tile_kernel<4, KIND, U, SHARE>;
+    case 8: return xorpir_tile_kernel<8, KIND, U, SHARE>;
+    case 16: return xorpir_tile_kernel<16, KIND, U, SHARE>;
+    case 24: return xorpir_tile_kernel<24, KIND, U, SHARE>;
+    case 32: return xorpir_tile_kernel<32, KIND, U, SHARE>;
     default: return nullptr;
     }
 }
 
 template <int KIND>
-TileFn pick_tile_u(uint32_t T, uint32_t U)
+TileFn pick_tile_u(uint32_t T, uint32_t U, bool share)
 {
     switch (U) {
-    case 4: return pick_tile<KIND, 4>(T);
-    case 8: return pick_tile<KIND, 8>(T);
-    case 16: return pick_tile<KIND, 16>(T);
+    case 4: return share ? pick_tile<KIND, 4, true>(T) : pick_tile<KIND, 4, false>(T);
+    case 8: return share ? pick_tile<KIND, 8, true>(T) : pick_tile<KIND, 8, false>(T);
+    case 16: return share ? nullptr : pick_tile<KIND, 16, false>(T);
     default: return nullptr;
     }
 }
 
 TileFn tile_fn(const Plan &p)
 {
+    const bool share = p.flags & PLAN_SHARED_COLUMN;
     if (p.kind == KIND_MASK)
-        return pick_tile_u<KIND_MASK>(p.tile, p.unroll);
+        return pick_tile_u<KIND_MASK>(p.tile, p.unroll, share);
     if (p.kind == KIND_SKIP)
-        return pick_tile_u<KIND_SKIP>(p.tile, p.unroll);
+        return pick_tile_u<KIND_SKIP>(p.tile, p.unroll, share);
     return nullptr;
 }
 
@@ -350,8 +366,10 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.B = g.B;
     a.Q = static_cast<const uint32_t *>(g.Q);
     a.qpitch_w = g.qpitch / 4;
-    a.n_rt = (g.B + p.tile - 1) / p.tile;
-    a.n_cg = (a.stride16 + COLS_PER_WG - 1) / COLS_PER_WG;
+    const bool share = p.flags & PLAN_SHARED_COLUMN;
+    const uint32_t rows_per_wg = p.tile * (share ? 4u : 1u);
+    a.n_rt = (g.B + rows_per_wg - 1) / rows_per_wg;
+    a.n_cg = share ? (a.stride16 + 63) / 64 : (a.stride16 + COLS_PER_WG - 1) / COLS_PER_WG;
     a.splits = p.splits;
     const uint64_t nwords = (g.n + 31) / 32;
     a.words_per_split = (uint32_t)((nwords + p.splits - 1) / p.splits);

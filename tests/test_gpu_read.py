@@ -40,31 +40,41 @@ def test_small_workload_every_tile_schedule(kind):
     want8 = oracle.pir_read(D, req8, threads=8)
     want37 = oracle.pir_read(D, req37, threads=8)
     with _db(D, d, z) as db:
-        for t in TILES:
-            for u in (4, 8, 16):
-                for s in (1, 0, 7):
-                    say(f"kind={kind} tile={t} unroll={u} splits={s}")
-                    db.set_plan(kind, t, s, u)
-                    assert_rows_equal(db.read(req8), want8, f"B=8 kind={kind} T={t} U={u} S={s}")
-                    assert_rows_equal(db.read(req37), want37, f"B=37 kind={kind} T={t} U={u} S={s}")
+        for fl in (0, pir.PLAN_SHARED_COLUMN):
+            for t in TILES:
+                for u in (4, 8, 16):
+                    if fl and (t < 4 or u == 16):
+                        with pytest.raises(pir.PirError):
+                            db.set_plan(kind, t, 0, u, fl)   # not compiled for this layout
+                        continue
+                    for s in (1, 0, 7):
+                        say(f"kind={kind} tile={t} unroll={u} splits={s} flags={fl}")
+                        db.set_plan(kind, t, s, u, fl)
+                        assert_rows_equal(db.read(req8), want8, f"B=8 kind={kind} T={t} U={u} S={s} F={fl}")
+                        assert_rows_equal(db.read(req37), want37, f"B=37 kind={kind} T={t} U={u} S={s} F={fl}")
 
 
 M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
+WIDE_SHAPES = [(4, 32), (8, 16), (8, 32), (16, 16)]
+FOUR_RUSSIANS = [(pir.KERNEL_M4R, s) for s in M4R_SHAPES] + [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES]
 
 
-def test_four_russians_every_shape():
-    """Four-Russians kernel: every (waves, requests/wave) shape, splits, ragged B."""
+@pytest.mark.parametrize("kind", [pir.KERNEL_M4R, pir.KERNEL_M4R_WIDE])
+def test_four_russians_every_shape(kind):
+    """Four-Russians kernels: every (waves, requests/wave) shape, splits, ragged B."""
     n, d, z = 1024, 4, 1024
     D = synth.uniform_db(1001, n, d * z)
     reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300)}
     wants = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
     with _db(D, d, z) as db:
-        for nw, tw in M4R_SHAPES:
+        for k, (nw, tw) in FOUR_RUSSIANS:
+            if k != kind:
+                continue
             for sp in (1, 0, 7):
-                db.set_plan(pir.KERNEL_M4R, tw, sp, nw)
+                db.set_plan(kind, tw, sp, nw)
                 for B, r in reqs.items():
-                    say(f"m4r nw={nw} tw={tw} splits={sp} B={B}")
-                    assert_rows_equal(db.read(r), wants[B], f"m4r nw={nw} tw={tw} S={sp} B={B}")
+                    say(f"kind={kind} nw={nw} tw={tw} splits={sp} B={B}")
+                    assert_rows_equal(db.read(r), wants[B], f"kind={kind} nw={nw} tw={tw} S={sp} B={B}")
 
 
 @pytest.mark.parametrize("n,d,z,B", [(37, 3, 20, 5), (1000, 1, 8, 70), (333, 2, 520, 17), (4097, 4, 1024, 133),
@@ -77,6 +87,10 @@ def test_four_russians_ragged_shapes(n, d, z, B):
         for nw, tw in ((4, 32), (8, 16), (16, 32)):
             db.set_plan(pir.KERNEL_M4R, tw, 0, nw)
             assert_rows_equal(db.read(req), want, f"m4r nw={nw} tw={tw}")
+        for nw, tw in WIDE_SHAPES:
+            for sp in (0, 3):
+                db.set_plan(pir.KERNEL_M4R_WIDE, tw, sp, nw)
+                assert_rows_equal(db.read(req), want, f"m4r-wide nw={nw} tw={tw} S={sp}")
 
 
 def test_four_russians_one_hot_and_densities():
@@ -85,11 +99,12 @@ def test_four_russians_one_hot_and_densities():
     idx = [0, 1, 7, 8, 31, 32, 33, 63, 64, 255, 256, 511, 512, 991, 992, 998, 999]
     onehot = synth.bits_to_rows(np.eye(n, dtype=bool)[idx])
     with _db(D, d, z) as db:
-        db.set_plan(pir.KERNEL_M4R, 16, 0, 8)
-        assert_rows_equal(db.read(onehot), D[idx], "m4r one-hot")
-        for p in (0.0, 0.01, 0.99, 1.0):
-            req = synth.bernoulli_requests(36, 70, n, p=p)
-            assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"m4r p={p}")
+        for kind, nw in ((pir.KERNEL_M4R, 8), (pir.KERNEL_M4R_WIDE, 8)):
+            db.set_plan(kind, 16, 0, nw)
+            assert_rows_equal(db.read(onehot), D[idx], f"kind={kind} one-hot")
+            for p in (0.0, 0.01, 0.99, 1.0):
+                req = synth.bernoulli_requests(36, 70, n, p=p)
+                assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"kind={kind} p={p}")
 
 
 @pytest.mark.parametrize("p", [0.0, 0.01, 0.5, 0.99, 1.0])
@@ -128,6 +143,8 @@ def test_ragged_shapes(n, d, z, B):
             for t in (1, 8, 32):
                 db.set_plan(kind, t, 0, 8)
                 assert_rows_equal(db.read(req), want, f"kind={kind} T={t}")
+            db.set_plan(kind, 8, 0, 4, pir.PLAN_SHARED_COLUMN)
+            assert_rows_equal(db.read(req), want, f"kind={kind} shared column")
 
 
 def test_padding_bits_ignored_and_empty_batch():
