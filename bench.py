@@ -39,6 +39,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = {1: "xorpir_tile.hip", 2: "xorpir_tile.hip", 3: "xorpir_m4r.hip", 4: "xorpir_m4rw.hip"}
+
+
+def kernel_source_digest(kind: int) -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2001_08250_amd", "csrc", KERNEL_SOURCES.get(kind, ""))
+    if not os.path.isfile(path):
+        return ""
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, plan) -> float | None:
+    """HBM bytes per read launch from the committed counter summary, or None when
+    no summary matches this workload and plan or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.isfile(path):
+        return None
+    t = json.load(open(path))
+    want = {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll, "flags": plan.flags}
+    if t.get("plan") != want or t.get("kernel_source_sha256_16") != kernel_source_digest(plan.kind):
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
 def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
     bits = np.unpackbits(req, axis=1, bitorder="little")[:, :n]
     return bits.sum(axis=1, dtype=np.int64)
@@ -109,17 +133,77 @@ def serve_bench(args, pir):
     print(json.dumps(line), flush=True)
 
 
+def stream_bench(args, pir, torch):
+    """Uneven batches: n = 2^20 x 4 KiB, batch sizes uniform in [1, 1024]."""
+    w = configs.C3
+    nb = args.batches or w.batches
+    sizes = synth.batch_sizes(w.batch_seed, nb)
+    total = int(sizes.sum())
+    t = time.perf_counter()
+    D = synth.uniform_db(w.db_seed, w.n, w.bucket_bytes, threads=16)
+    db = pir.PirDB(w.n, w.d, w.z)
+    db.load(D)
+    del D
+    pool = synth.bernoulli_requests(w.req_seed, 1024, w.n)
+    rng = np.random.default_rng(w.batch_seed)
+    first = np.array([rng.integers(0, 1024 - s + 1) for s in sizes], dtype=np.uint64)
+    log(f"[stream] {nb} batches, {total} reads; database ready in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(pool).to(dev)
+    out = torch.empty((total, w.bucket_bytes), dtype=torch.uint8, device=dev)
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    res = {}
+    # (a) persistent work-queue kernel, graph captured on the first call and replayed
+    db.read_stream_async(q, sizes, out, req_first=first)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        db.read_stream_async(q, sizes, out, req_first=first)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res["persistent_graph"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
+    # (b) one launch sequence per batch with the planner's schedule for its size
+    if args.tune:
+        for Bt in (1, 4, 16, 64, 256, 1024):
+            p, us = db.tune(Bt, iters=2)
+            log(f"[stream] tuned B={Bt}: {p} {us:.0f} us")
+    def per_batch():
+        for k in range(nb):
+            b = int(sizes[k])
+            f = int(first[k])
+            db.read_async(q[f:f + b], out[starts[k]:starts[k] + b])
+    per_batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        per_batch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res["per_batch_launch"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
+    log(f"[stream] {res}")
+    best = max(res.values(), key=lambda r: r["reads_per_s"])
+    line = {"metric": "PIR bucket-reads/sec (uneven batch stream)", "value": best["reads_per_s"], "unit": "reads/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": best["ms_per_stream"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "batches": nb,
+                       "reads": total, "parallelism": "single-gpu"},
+            "stream": res}
+    print(json.dumps(line), flush=True)
+    db.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4a", "c4b", "c3b", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4a", "c4b", "c3b", "c5"])
     ap.add_argument("--duration", type=float, default=3.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--baseline-s", type=float, default=1.0, help="serving: seconds of the one-per-read baseline")
     ap.add_argument("--max-batch", type=int, default=1024, help="serving: reads per launch")
     ap.add_argument("--rates", type=int, nargs="*", default=[], help="serving: subset of the arrival rates")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--batches", type=int, default=0, help="uneven stream: number of batches (default 500)")
     ap.add_argument("--step", default="", choices=["", "full", "read"],
                     help="full = writes + commit + read + interest fetch (default for cuckoo workloads)")
     ap.add_argument("--B", type=int, default=0, help="override the batch size")
@@ -146,6 +230,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c5":
         return serve_bench(args, pir)
+    if args.workload == "c3":
+        return stream_bench(args, pir, torch)
     w = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B, "c3b": configs.C3}[args.workload]
     B = args.B or w.B or 1024
     full = (args.step or ("full" if w.fill == "cuckoo" else "read")) == "full"
@@ -209,14 +295,10 @@ def main():
         db.interest_add(ipos[sl])
         db.commit()
 
-    def step(k, ev=None):
+    def step(k):
         if full:
             do_writes(k)
-        if ev is not None:
-            ev[0].record(stream)
         db.read_async(q, out)
-        if ev is not None:
-            ev[1].record(stream)
         if full:
             L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), sh)
 
@@ -230,14 +312,19 @@ def main():
     for k in range(W):
         step(k)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    # The library records HIP events on the read's own stream right around
+    # the main read kernel of every read in the timed region.
+    db.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        step(W + k, evs[k])
+        step(W + k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kern = db.profile_collect()
+    db.profile_enable(False)
+    assert kern.size == min(K, pir.PROFILE_MAX)
+    kern_ms = float(np.mean(kern))
     got = out.cpu().numpy()
     got_iv = iv.cpu().numpy()
 
@@ -257,8 +344,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    roof["traffic"] = measured_traffic(w.name, plan)
     roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
-                plain_xor_tops=round(alu_achieved, 3))
+                plain_xor_tops=round(alu_achieved, 3), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
 
     cpu = None
     parity = None

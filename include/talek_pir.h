@@ -164,7 +164,8 @@ enum pir_kernel_kind {
 /* Plan flags. SHARED_COLUMN (MASK and SKIP families): the four waves of a
  * workgroup stream the same 1 KiB column chunk of D and take four
  * consecutive request tiles, so the chunk is read from L2 once per
- * workgroup instead of once per wave. */
+ * workgroup instead of once per wave. Bits 8..11 (M4R_WIDE): how many
+ * bucket groups ahead D is loaded (0 = 2). */
 enum { PIR_PLAN_SHARED_COLUMN = 1 };
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
@@ -196,6 +197,20 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
 /* Save / load the tuning table as JSON. Loading merges into the table. */
 int pir_tune_save(const char *path);
 int pir_tune_load(const char *path);
+
+/*
+ * Kernel timing. While enabled (on != 0), every read of this handle issued by
+ * pir_read_batch or pir_read_batch_async records a HIP event pair on its
+ * stream right around the main read kernel (not the request staging or the
+ * split reduction), for the first PIR_PROFILE_MAX reads after the enable;
+ * later reads are not recorded. Enabling clears earlier records.
+ * pir_profile_collect waits for the recorded reads to finish, writes up to
+ * cap durations in milliseconds (in issue order) into ms, the number of
+ * recorded reads into *count (may be NULL), and clears the records.
+ */
+enum { PIR_PROFILE_MAX = 4096 };
+int pir_profile_enable(pir_db *db, int on);
+int pir_profile_collect(pir_db *db, float *ms, uint32_t cap, uint32_t *count);
 
 /* ------------------------------------------------- private notifications */
 

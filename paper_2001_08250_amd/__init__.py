@@ -25,6 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "talek_pir.h")
 PIR_OK, PIR_EINVAL, PIR_ERANGE, PIR_ENOMEM, PIR_EDEVICE, PIR_EFULL, PIR_EBUSY = 0, -1, -2, -3, -4, -5, -6
 KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R, KERNEL_M4R_WIDE = 0, 1, 2, 3, 4
 PLAN_SHARED_COLUMN = 1
+PROFILE_MAX = 4096
 
 
 class PirError(RuntimeError):
@@ -96,6 +97,9 @@ SIGNATURES = {
     "pir_tune": (ctypes.c_int, [_vp, _u32, _u32, ctypes.POINTER(pir_plan), ctypes.POINTER(ctypes.c_double)]),
     "pir_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "pir_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "pir_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "pir_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_uint32,
+                                           ctypes.POINTER(ctypes.c_uint32)]),
     "pir_interest_config": (ctypes.c_int, [_vp, _u64, _u32]),
     "pir_interest_add": (ctypes.c_int, [_vp, _u32p, _u32]),
     "pir_interest_vector": (ctypes.c_int, [_vp, _u8p, _u64]),
@@ -271,6 +275,17 @@ class PirDB:
         p = pir_plan()
         _check(self._L.pir_get_plan(self.h, B, ctypes.byref(p)), "pir_get_plan")
         return p
+
+    def profile_enable(self, on: bool = True):
+        _check(self._L.pir_profile_enable(self.h, 1 if on else 0), "pir_profile_enable")
+
+    def profile_collect(self) -> np.ndarray:
+        """Main read kernel durations (ms) of the reads since profile_enable."""
+        buf = np.zeros(PROFILE_MAX, dtype=np.float32)
+        cnt = ctypes.c_uint32(0)
+        _check(self._L.pir_profile_collect(self.h, _ptr(buf, ctypes.c_float), PROFILE_MAX, ctypes.byref(cnt)),
+               "pir_profile_collect")
+        return buf[:cnt.value].copy()
 
     def tune(self, B: int, iters: int = 5):
         p = pir_plan()

@@ -98,6 +98,10 @@ struct pir_db {
     hipEvent_t upload_ev[3] = {nullptr, nullptr, nullptr};
     bool upload_pending[3] = {false, false, false};
     uint64_t *mirror_idx_host = nullptr;  // pinned
+    // kernel timing (pir_profile_*): event pairs, created on first use
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    size_t prof_used = 0;
     uint64_t mirror_idx_cap = 0;
 };
 

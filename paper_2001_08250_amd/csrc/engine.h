@@ -53,8 +53,11 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus);
 bool plan_supported(const Plan &p);
 
 // Enqueue the read: kernels on `stream`; `partials` must hold
-// partial_bytes(g, p) bytes when p.splits > 1.
-hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+// partial_bytes(g, p) bytes. When ev_begin / ev_end are given they are
+// recorded right before and right after the main read kernel (not the
+// staging or split-reduction kernels).
+hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream,
+                       hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 // --- epoch writes ------------------------------------------------------
 // dst[idx[e]] = src[e] for e < count; each entry `stride` bytes, 16-aligned.

@@ -262,6 +262,10 @@ void free_db(pir_db *db)
             hipEventDestroy(db->upload_ev[i]);
     if (db->mirror_idx_host)
         hipHostFree(db->mirror_idx_host);
+    for (auto &ev : db->prof_ev) {
+        hipEventDestroy(ev.first);
+        hipEventDestroy(ev.second);
+    }
     if (db->stream)
         hipStreamDestroy(db->stream);
     if (db->capture_stream)
@@ -518,6 +522,28 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 
 uint64_t pir_epoch(const pir_db *db) { return db ? db->epoch : 0; }
 
+// Next timing event pair for a read, or {nullptr, nullptr} when timing is
+// off or the record is full.
+static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
+{
+    *eb = *ee = nullptr;
+    if (!db->prof_on || db->prof_used >= PIR_PROFILE_MAX)
+        return PIR_OK;
+    if (db->prof_used == db->prof_ev.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        HIP_TRY(hipEventCreate(&a));
+        if (hipEventCreate(&b) != hipSuccess) {
+            hipEventDestroy(a);
+            return PIR_EDEVICE;
+        }
+        db->prof_ev.emplace_back(a, b);
+    }
+    *eb = db->prof_ev[db->prof_used].first;
+    *ee = db->prof_ev[db->prof_used].second;
+    ++db->prof_used;
+    return PIR_OK;
+}
+
 int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp)
 {
     if (!db)
@@ -536,7 +562,9 @@ int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *res
     ReadGeom g = read_geom(db, sc.req, db->qpitch, B, sc.resp, db->stride);
     Plan p = choose_plan(db, B);
     PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
-    HIP_TRY(launch_read(g, p, sc.part, db->stream));
+    hipEvent_t eb, ee;
+    PIR_TRY(profile_slot(db, &eb, &ee));
+    HIP_TRY(launch_read(g, p, sc.part, db->stream, eb, ee));
     HIP_TRY(hipMemcpy2DAsync(resp, db->bucket_bytes, sc.resp, db->stride, db->bucket_bytes, B,
                              hipMemcpyDeviceToHost, db->stream));
     HIP_TRY(hipStreamSynchronize(db->stream));
@@ -579,7 +607,9 @@ int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint
     ReadGeom g = read_geom(db, q, qp, B, out, op);
     Plan p = choose_plan(db, B);
     PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
-    HIP_TRY(launch_read(g, p, sc.part, s));
+    hipEvent_t eb, ee;
+    PIR_TRY(profile_slot(db, &eb, &ee));
+    HIP_TRY(launch_read(g, p, sc.part, s, eb, ee));
     if (!direct)
         HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,
                                  hipMemcpyDeviceToDevice, s));
@@ -673,3 +703,31 @@ int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void 
 }
 
 }  // extern "C"
+
+int pir_profile_enable(pir_db *db, int on)
+{
+    if (!db)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    db->prof_on = on != 0;
+    db->prof_used = 0;
+    return PIR_OK;
+}
+
+int pir_profile_collect(pir_db *db, float *ms, uint32_t cap, uint32_t *count)
+{
+    if (!db || (cap && !ms))
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    const size_t used = db->prof_used;
+    for (size_t i = 0; i < used; ++i) {
+        HIP_TRY(hipEventSynchronize(db->prof_ev[i].second));
+        if (i < cap)
+            HIP_TRY(hipEventElapsedTime(&ms[i], db->prof_ev[i].first, db->prof_ev[i].second));
+    }
+    if (count)
+        *count = (uint32_t)used;
+    db->prof_used = 0;
+    return PIR_OK;
+}

@@ -6,13 +6,16 @@
 namespace talek {
 
 bool tile_plan_supported(const Plan &p);
-hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                            hipEvent_t ee);
 bool m4r_plan_supported(const Plan &p);
-hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                           hipEvent_t ee);
 uint32_t m4r_tasks(const ReadGeom &g, const Plan &p);
 uint64_t m4r_staging_bytes(const ReadGeom &g);
 bool m4rw_plan_supported(const Plan &p);
-hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream);
+hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                            hipEvent_t ee);
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p);
 uint64_t m4rw_staging_bytes(const ReadGeom &g);
 uint64_t m4rw_groups(uint64_t n);
@@ -99,15 +102,16 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
     return p;
 }
 
-hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t ev_begin,
+                       hipEvent_t ev_end)
 {
     if (g.B == 0)
         return hipSuccess;
     if (p.kind == KIND_M4R)
-        return launch_m4r_read(g, p, partials, stream);
+        return launch_m4r_read(g, p, partials, stream, ev_begin, ev_end);
     if (p.kind == KIND_M4RW)
-        return launch_m4rw_read(g, p, partials, stream);
-    return launch_tile_read(g, p, partials, stream);
+        return launch_m4rw_read(g, p, partials, stream, ev_begin, ev_end);
+    return launch_tile_read(g, p, partials, stream, ev_begin, ev_end);
 }
 
 }  // namespace talek

@@ -116,9 +116,10 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
             }
         }
     }
-    for (uint32_t nw : {4u, 8u, 16u}) {
+    for (uint32_t nw : {4u, 8u, 16u})
+    for (uint32_t depth : {2u, 3u, 4u}) {
         for (uint32_t t : {16u, 32u}) {
-            Plan base = resolve_plan(g, Plan{KIND_M4RW, t, 0, nw, 0}, db->num_cus);
+            Plan base = resolve_plan(g, Plan{KIND_M4RW, t, 0, nw, depth << 8}, db->num_cus);
             for (uint32_t sm : {1u, 2u}) {
                 Plan a = base, b = base;
                 a.splits = std::max<uint32_t>(1, base.splits / sm);

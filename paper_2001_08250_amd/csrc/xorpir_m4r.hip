@@ -236,7 +236,8 @@ uint32_t m4r_tasks(const ReadGeom &g, const Plan &p)
     return ((g.B + R - 1) / R) * slices;
 }
 
-hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                     hipEvent_t ee)
 {
     M4rFn fn = m4r_fn(p.unroll, p.tile);
     if (!fn)
@@ -271,8 +272,12 @@ hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hip
     }
     const uint64_t tasks = (uint64_t)a.n_rt * a.n_slices * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
+    if (eb && hipEventRecord(eb, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ee)
+        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);

@@ -96,12 +96,12 @@ __device__ __forceinline__ void build_table(uint4 *__restrict__ tbl, const uint4
     }
 }
 
-// Lookups in batches of 8: eight ds_read_b128 in flight per wave before the
-// first XOR, to cover the LDS latency.
-template <int TW>
+// Lookups in batches: BATCH ds_read_b128 in flight per wave before the first
+// XOR, to cover the LDS latency (4 for 16-wave workgroups, whose waves are
+// limited to 128 VGPRs, else 8).
+template <int TW, int BATCH>
 __device__ __forceinline__ void lookup(uint4 (&acc)[TW], const uint8_t *tbl, const uint32_t *__restrict__ off)
 {
-    constexpr int BATCH = TW < 8 ? TW : 8;
 #pragma unroll
     for (int r0 = 0; r0 < TW; r0 += BATCH) {
         uint4 t[BATCH];
@@ -114,28 +114,63 @@ __device__ __forceinline__ void lookup(uint4 (&acc)[TW], const uint8_t *tbl, con
     }
 }
 
-// Group step for group x (K = parity of x - first group): refill ring[K]
-// (group x, already built) with group x + 2, build group x + 1 into the other
-// buffer, look up group x, synchronise. Loads and builds past the range are
-// harmless (readable padding rows, a table nobody reads) and keep the code
-// straight-line so the waits stay exact.
-template <int NW, int TW, int K>
-__device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[2][GB], uint4 *lds,
+// Group step for group x, K = (x - first group) mod U with U = lcm(P, 2):
+// ring[K % P] held group x (already built) and is refilled with group x + P,
+// so D loads run P - 1 steps ahead of their use; then group x + 1 (in
+// ring[(K + 1) % P]) is built into the other table buffer, group x is looked
+// up from buffer K & 1, and the workgroup synchronises. Loads and builds past
+// the range are harmless (readable padding rows, a table nobody reads) and
+// keep the code straight-line so the waits stay exact.
+template <int NW, int TW, int P, int K>
+__device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
                                            const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
                                            uint64_t x, const uint32_t *__restrict__ q, bool active, uint32_t wave,
                                            uint32_t lane)
 {
-    load_group(ring[K], D, row_bytes, lane_off, x + 2);
-    build_table<NW>(lds + (K ^ 1) * TABLE_U4, ring[K ^ 1], wave, lane);
+    constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
+    load_group(ring[slot], D, row_bytes, lane_off, x + P);
+    build_table<NW>(lds + (buf ^ 1) * TABLE_U4, ring[next], wave, lane);
     if (active)
-        lookup<TW>(acc, reinterpret_cast<const uint8_t *>(lds + K * TABLE_U4 + lane), q);
+        lookup<TW, (NW >= 16 ? 4 : 8)>(acc, reinterpret_cast<const uint8_t *>(lds + buf * TABLE_U4 + lane), q);
     __syncthreads();
 }
 
-template <int NW, int TW>
+template <int NW, int TW, int P, int K, int U>
+__device__ __forceinline__ void group_steps(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
+                                            const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
+                                            uint64_t x, const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
+                                            uint32_t wave, uint32_t lane)
+{
+    if constexpr (K < U) {
+        group_step<NW, TW, P, K>(acc, ring, lds, D, row_bytes, lane_off, x + K, Qw + (x + K) * Bp, active, wave,
+                                 lane);
+        group_steps<NW, TW, P, K + 1, U>(acc, ring, lds, D, row_bytes, lane_off, x, Qw, Bp, active, wave, lane);
+    }
+}
+
+// Tail: the first `left` (< U) steps of an unrolled iteration.
+template <int NW, int TW, int P, int K, int U>
+__device__ __forceinline__ void group_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
+                                                 const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                                 uint32_t lane_off, uint64_t x, uint64_t left,
+                                                 const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
+                                                 uint32_t wave, uint32_t lane)
+{
+    if constexpr (K < U) {
+        if ((uint64_t)K < left) {
+            group_step<NW, TW, P, K>(acc, ring, lds, D, row_bytes, lane_off, x + K, Qw + (x + K) * Bp, active,
+                                     wave, lane);
+            group_steps_tail<NW, TW, P, K + 1, U>(acc, ring, lds, D, row_bytes, lane_off, x, left, Qw, Bp, active,
+                                                  wave, lane);
+        }
+    }
+}
+
+template <int NW, int TW, int P>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, NW / 4)))
 void xorpir_m4rw_kernel(const WideArgs a)
 {
+    constexpr int U = (P % 2 == 0) ? P : 2 * P;  // lcm(P, 2)
     __shared__ uint4 lds[2 * TABLE_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
@@ -163,20 +198,20 @@ void xorpir_m4rw_kernel(const WideArgs a)
         acc[r] = make_uint4(0u, 0u, 0u, 0u);
 
     if (gb < ge) {
-        uint4 ring[2][GB];
-        load_group(ring[0], a.D, a.row_bytes, lane_off, gb);
-        load_group(ring[1], a.D, a.row_bytes, lane_off, gb + 1);
+        uint4 ring[P][GB];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            load_group(ring[k], a.D, a.row_bytes, lane_off, gb + k);
         build_table<NW>(lds, ring[0], wave, lane);
         __syncthreads();
         const uint32_t *Qw = a.Qs + r0;
         uint64_t x = gb;
-        for (; x + 2 <= ge; x += 2) {
-            group_step<NW, TW, 0>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw + x * a.Bp, active, wave, lane);
-            group_step<NW, TW, 1>(acc, ring, lds, a.D, a.row_bytes, lane_off, x + 1, Qw + (x + 1) * a.Bp, active,
-                                  wave, lane);
-        }
+        for (; x + U <= ge; x += U)
+            group_steps<NW, TW, P, 0, U>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw, a.Bp, active, wave,
+                                         lane);
         if (x < ge)
-            group_step<NW, TW, 0>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw + x * a.Bp, active, wave, lane);
+            group_steps_tail<NW, TW, P, 0, U>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, ge - x, Qw, a.Bp,
+                                              active, wave, lane);
     }
 
     if (active && col_ok) {
@@ -220,14 +255,21 @@ __global__ __launch_bounds__(256) void stage_wide_offsets_kernel(const uint32_t 
 
 using WideFn = void (*)(const WideArgs);
 
-WideFn wide_fn(uint32_t nw, uint32_t tw)
+// Prefetch depth comes from plan flags bits 8..11 (0 = 2 groups).
+WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth)
 {
-    if (nw == 4 && tw == 32) return xorpir_m4rw_kernel<4, 32>;
-    if (nw == 8 && tw == 16) return xorpir_m4rw_kernel<8, 16>;
-    if (nw == 8 && tw == 32) return xorpir_m4rw_kernel<8, 32>;
-    if (nw == 16 && tw == 16) return xorpir_m4rw_kernel<16, 16>;
+    if (depth == 0)
+        depth = 2;
+    if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2>;
+    if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<8, 16, 2>;
+    if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rw_kernel<8, 16, 4>;
+    if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2>;
+    if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rw_kernel<8, 32, 3>;
+    if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2>;
     return nullptr;
 }
+
+uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
 
 uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
@@ -235,7 +277,7 @@ uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
 // Plan fields for this family: tile = requests per wave (TW), unroll = waves
 // per workgroup (NW).
-bool m4rw_plan_supported(const Plan &p) { return wide_fn(p.unroll, p.tile) != nullptr; }
+bool m4rw_plan_supported(const Plan &p) { return wide_fn(p.unroll, p.tile, plan_depth(p)) != nullptr; }
 
 uint64_t m4rw_staging_bytes(const ReadGeom &g)
 {
@@ -253,9 +295,10 @@ uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
 
 uint64_t m4rw_groups(uint64_t n) { return (n + GB - 1) / GB; }
 
-hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                     hipEvent_t ee)
 {
-    WideFn fn = wide_fn(p.unroll, p.tile);
+    WideFn fn = wide_fn(p.unroll, p.tile, plan_depth(p));
     if (!fn)
         return hipErrorInvalidValue;
     WideArgs a{};
@@ -292,8 +335,12 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     }
     const uint64_t tasks = (uint64_t)a.n_rt * a.slices * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
+    if (eb && hipEventRecord(eb, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ee)
+        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);

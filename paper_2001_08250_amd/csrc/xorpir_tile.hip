@@ -335,7 +335,7 @@ uint32_t queue_grid(int num_cus) { return (uint32_t)std::max(num_cus, 1) * 4; }
 
 hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(xorpir_queue_kernel<KIND_MASK>, dim3(grid), dim3(WG), 0, stream, g);
+    hipLaunchKernelGGL(xorpir_queue_kernel<KIND_SKIP>, dim3(grid), dim3(WG), 0, stream, g);
     return hipGetLastError();
 }
 
@@ -354,7 +354,8 @@ hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, 
     return hipGetLastError();
 }
 
-hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream)
+hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
+                     hipEvent_t ee)
 {
     TileFn fn = tile_fn(p);
     if (!fn)
@@ -385,8 +386,12 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
     const uint64_t tasks = (uint64_t)a.n_rt * a.n_cg * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
     const uint32_t grid = a.tasks_per_xcd * 8;
+    if (eb && hipEventRecord(eb, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(WG), 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ee)
+        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);

@@ -37,6 +37,8 @@ def test_validation_without_device():
     assert L.pir_read_batch(None, None, 0, None) == pir.PIR_EINVAL
     assert L.pir_epoch_commit(None, None) == pir.PIR_EINVAL
     assert L.pir_cuckoo_create(None, 0, 0, 500, ctypes.byref(h)) == pir.PIR_EINVAL
+    assert L.pir_profile_enable(None, 1) == pir.PIR_EINVAL
+    assert L.pir_profile_collect(None, None, 0, None) == pir.PIR_EINVAL
     L.pir_db_destroy(None)  # NULL-safe
 
 

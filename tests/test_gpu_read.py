@@ -55,8 +55,9 @@ def test_small_workload_every_tile_schedule(kind):
 
 
 M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
-WIDE_SHAPES = [(4, 32), (8, 16), (8, 32), (16, 16)]
-FOUR_RUSSIANS = [(pir.KERNEL_M4R, s) for s in M4R_SHAPES] + [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES]
+WIDE_SHAPES = [(4, 32, 2), (8, 16, 2), (8, 16, 4), (8, 32, 2), (8, 32, 3), (16, 16, 2)]  # waves, tile, depth
+FOUR_RUSSIANS = ([(pir.KERNEL_M4R, (nw, tw, 0)) for nw, tw in M4R_SHAPES] +
+                 [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES])
 
 
 @pytest.mark.parametrize("kind", [pir.KERNEL_M4R, pir.KERNEL_M4R_WIDE])
@@ -67,14 +68,14 @@ def test_four_russians_every_shape(kind):
     reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300)}
     wants = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
     with _db(D, d, z) as db:
-        for k, (nw, tw) in FOUR_RUSSIANS:
+        for k, (nw, tw, depth) in FOUR_RUSSIANS:
             if k != kind:
                 continue
             for sp in (1, 0, 7):
-                db.set_plan(kind, tw, sp, nw)
+                db.set_plan(kind, tw, sp, nw, depth << 8)
                 for B, r in reqs.items():
-                    say(f"kind={kind} nw={nw} tw={tw} splits={sp} B={B}")
-                    assert_rows_equal(db.read(r), wants[B], f"kind={kind} nw={nw} tw={tw} S={sp} B={B}")
+                    say(f"kind={kind} nw={nw} tw={tw} depth={depth} splits={sp} B={B}")
+                    assert_rows_equal(db.read(r), wants[B], f"kind={kind} nw={nw} tw={tw} P={depth} S={sp} B={B}")
 
 
 @pytest.mark.parametrize("n,d,z,B", [(37, 3, 20, 5), (1000, 1, 8, 70), (333, 2, 520, 17), (4097, 4, 1024, 133),
@@ -87,10 +88,10 @@ def test_four_russians_ragged_shapes(n, d, z, B):
         for nw, tw in ((4, 32), (8, 16), (16, 32)):
             db.set_plan(pir.KERNEL_M4R, tw, 0, nw)
             assert_rows_equal(db.read(req), want, f"m4r nw={nw} tw={tw}")
-        for nw, tw in WIDE_SHAPES:
+        for nw, tw, depth in WIDE_SHAPES:
             for sp in (0, 3):
-                db.set_plan(pir.KERNEL_M4R_WIDE, tw, sp, nw)
-                assert_rows_equal(db.read(req), want, f"m4r-wide nw={nw} tw={tw} S={sp}")
+                db.set_plan(pir.KERNEL_M4R_WIDE, tw, sp, nw, depth << 8)
+                assert_rows_equal(db.read(req), want, f"m4r-wide nw={nw} tw={tw} P={depth} S={sp}")
 
 
 def test_four_russians_one_hot_and_densities():
@@ -273,3 +274,28 @@ def test_tuner_picks_a_correct_plan(tmp_path):
         path = str(tmp_path / "tune.json")
         assert pir.lib().pir_tune_save(path.encode()) == 0
         assert pir.lib().pir_tune_load(path.encode()) == 0
+
+
+def test_kernel_timing_records_each_read():
+    import torch
+    n, d, z = 4096, 4, 1024
+    D = synth.uniform_db(91, n, d * z)
+    req = synth.bernoulli_requests(92, 64, n)
+    want = oracle.pir_read(D, req)
+    with _db(D, d, z) as db:
+        dev = torch.device("cuda:0")
+        q = torch.from_numpy(req).to(dev)
+        out = torch.zeros((64, d * z), dtype=torch.uint8, device=dev)
+        db.read_async(q, out)                      # not recorded: timing is off
+        db.profile_enable(True)
+        for _ in range(3):
+            db.read_async(q, out)
+        assert_rows_equal(db.read(req), want, "sync read while timing")
+        ms = db.profile_collect()
+        assert ms.size == 4 and np.all(ms > 0) and np.all(ms < 1000)
+        assert db.profile_collect().size == 0      # collect clears
+        db.profile_enable(False)
+        db.read_async(q, out)
+        assert db.profile_collect().size == 0
+        torch.cuda.synchronize()
+        assert_rows_equal(out.cpu().numpy(), want, "async read")
