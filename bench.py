@@ -32,6 +32,8 @@ from synth import configs  # noqa: E402
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit VALU lane-ops per second: 39.3 T
 INTEREST_K = 6
+IV_BITS = 1 << 17        # global interest vector: 16 KiB (the paper's ~14 KB at 1M messages)
+IV_WINDOW = 100          # deltas kept: the paper's TTL of 100 write intervals
 WRITE_FRAC = 0.1
 
 
@@ -61,6 +63,60 @@ def measured_traffic(workload: str, plan) -> float | None:
     if t.get("plan") != want or t.get("kernel_source_sha256_16") != kernel_source_digest(plan.kind):
         return None
     return float(t["hbm_bytes_per_launch"])
+
+
+KERNEL_NAMES = {1: "xorpir_tile_kernel", 2: "xorpir_tile_kernel", 3: "xorpir_m4r_kernel",
+                4: "xorpir_m4rw_kernel"}
+
+
+def _counter_rows(d: str, counter: str):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def _calibration_dispatch(rows):
+    """The plain copy that --calib-copy-mib runs right after filling its source."""
+    for a, b in zip(rows, rows[1:]):
+        if "elementwise_kernel" in a["Kernel_Name"] and b["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+            return float(b["Counter_Value"])
+    raise SystemExit("calibration copy not found (run the profiled bench with --calib-copy-mib)")
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str, calib_mib: int, command: str):
+    """Write profiles/traffic_<workload>.json: HBM bytes per launch of the main read
+    kernel from one FETCH_SIZE and one WRITE_SIZE rocprofv3 pass, each scaled by what
+    the same counter reads for a plain device copy of calib_mib MiB in the same run."""
+    line = json.loads([x for x in open(bench_json) if x.startswith("{")][-1])
+    plan = line["config"]["plan"]
+    name = KERNEL_NAMES[plan["kind"]]
+    out = {"workload": line["config"]["workload"], "plan": plan,
+           "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name,
+           "calibration_copy_kib": calib_mib * 1024, "command": command}
+    total = 0.0
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        copy_kib = _calibration_dispatch(rows)
+        factor = calib_mib * 1024 / copy_kib
+        vals = [float(r["Counter_Value"]) for r in rows if name in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"no {name} dispatches in {d}")
+        kib = float(np.mean(vals))
+        out[counter.lower()] = {"copy_kib": copy_kib, "factor": round(factor, 4), "kernel_kib_mean": kib,
+                                "dispatches": len(vals), "bytes": kib * factor * 1024}
+        total += kib * factor * 1024
+    out["hbm_bytes_per_launch"] = round(total)
+    path = os.path.join(ROOT, "profiles", f"traffic_{out['workload']}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
@@ -153,7 +209,8 @@ def stream_bench(args, pir, torch):
     out = torch.empty((total, w.bucket_bytes), dtype=torch.uint8, device=dev)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     res = {}
-    # (a) persistent work-queue kernel, graph captured on the first call and replayed
+    # (a) batches fused into launch groups of >= 256 requests, graph captured on
+    #     the first call and replayed
     db.read_stream_async(q, sizes, out, req_first=first)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -161,7 +218,7 @@ def stream_bench(args, pir, torch):
         db.read_stream_async(q, sizes, out, req_first=first)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    res["persistent_graph"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
+    res["fused_graph"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
     # (b) one launch sequence per batch with the planner's schedule for its size
     if args.tune:
         for Bt in (1, 4, 16, 64, 256, 1024):
@@ -217,7 +274,13 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
+                    help="no GPU: turn two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of a bench run "
+                         "made with --calib-copy-mib into profiles/traffic_<workload>.json")
+    ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with the summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        return traffic_summary(*args.traffic_summary, args.calib_copy_mib or 256, args.traffic_command)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one server's share runs on one "
@@ -241,7 +304,7 @@ def main():
     # ---- database -------------------------------------------------------
     t = time.perf_counter()
     db = pir.PirDB(w.n, w.d, w.z)
-    db.interest_config(1 << 20, 8)
+    db.interest_config(IV_BITS, IV_WINDOW)
     ck = None
     pre = None
     if w.fill == "cuckoo":
@@ -265,7 +328,7 @@ def main():
         else:
             wr = (None, synth.uniform_indices(w.req_seed + 5, total_w, w.n), None,
                   synth.uniform_bytes(w.req_seed + 6, total_w * w.bucket_bytes).reshape(total_w, w.bucket_bytes))
-        ipos = synth.interest_positions(w.req_seed + 7, total_w, INTEREST_K, 1 << 20)
+        ipos = synth.interest_positions(w.req_seed + 7, total_w, INTEREST_K, IV_BITS)
 
     req = synth.bernoulli_requests(w.req_seed, B, w.n)
     if args.kind:
@@ -279,26 +342,39 @@ def main():
     dev = torch.device("cuda:0")
     q = torch.from_numpy(req).to(dev)
     out = torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev)
-    iv = torch.empty(((1 << 20) // 8,), dtype=torch.uint8, device=dev)
+    iv = torch.empty((IV_BITS // 8,), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     L = pir.lib()
     sh = int(stream.cuda_stream)
 
+    # host seconds per part of the step, summed over the timed steps
+    host_s = {"insert": 0.0, "stage": 0.0, "interest_add": 0.0, "commit": 0.0, "read_call": 0.0}
+
     def do_writes(k):
         sl = slice(k * nw, (k + 1) * nw)
+        t0 = time.perf_counter()
         if ck is not None:
             ck.insert_many(wr[0][sl], wr[1][sl], wr[2][sl], wr[3][sl])
+            t1 = time.perf_counter()
             ck.stage()
         else:
             for i in range(sl.start, sl.stop):
                 db.write_bucket(int(wr[1][i]), wr[3][i])
+            t1 = time.perf_counter()
+        t2 = time.perf_counter()
         db.interest_add(ipos[sl])
+        t3 = time.perf_counter()
         db.commit()
+        t4 = time.perf_counter()
+        for key, dt in (("insert", t1 - t0), ("stage", t2 - t1), ("interest_add", t3 - t2), ("commit", t4 - t3)):
+            host_s[key] += dt
 
     def step(k):
         if full:
             do_writes(k)
+        t = time.perf_counter()
         db.read_async(q, out)
+        host_s["read_call"] += time.perf_counter() - t
         if full:
             L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), sh)
 
@@ -315,6 +391,8 @@ def main():
     # The library records HIP events on the read's own stream right around
     # the main read kernel of every read in the timed region.
     db.profile_enable(True)
+    for key in host_s:
+        host_s[key] = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -375,7 +453,7 @@ def main():
         if full:
             last = W + K - 1
             epochs = [np.zeros(0, np.uint32)] + [ipos[k * nw:(k + 1) * nw].reshape(-1) for k in range(W + K)]
-            want_iv = oracle.interest_window(1 << 20, epochs, last + 1, 8)
+            want_iv = oracle.interest_window(IV_BITS, epochs, last + 1, IV_WINDOW)
             parity = parity and bool(np.array_equal(want_iv, got_iv))
         cpu = {"value": round(len(rows) / dt, 2), "unit": "reads/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(rows)} of the {B} request rows of the last batch over the full "
@@ -404,6 +482,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sampled": parity,
+        "host_ms_per_step": {key: round(1e3 * v / K, 4) for key, v in host_s.items()},
     }
     print(json.dumps(line), flush=True)
     db.close()

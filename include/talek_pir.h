@@ -134,16 +134,17 @@ int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint
  * of d_req and writes response rows resp_first[k] .. of d_resp (row indices,
  * host arrays; a NULL array means the batches' rows are concatenated in
  * order). Every batch is answered exactly as pir_read_batch_async would
- * answer it. The work items of all batches (request tile x bucket split x
- * column group) go through one persistent work-queue kernel launch per chunk
- * of batches (a chunk is bounded by the split-partial scratch it needs),
- * claimed in batch order, so one batch's tail overlaps the next batch's head;
- * the launch sequence is captured in a HIP graph and replayed when the same
- * stream shape, buffers and snapshot repeat. Requires 4-byte aligned request
- * rows with req_pitch % 4 == 0 and ceil(n/8) % 4 == 0, and 16-byte aligned
- * response rows with resp_pitch % 16 == 0 and d * msg_bytes % 16 == 0
- * (PIR_EINVAL otherwise). (Section "Evaluation": read requests are batched
- * and forwarded to the GPU; the leader may reorder reads.)
+ * answer it. Consecutive batches are fused into launch groups of at least
+ * 256 requests (an answer depends only on its own request row and the
+ * snapshot), each answered by one read launch with that group's schedule;
+ * rows that are not contiguous are gathered into / scattered from library
+ * scratch on the stream. The launch sequence is captured in a HIP graph and
+ * replayed when the same stream shape, buffers, schedules and snapshot
+ * repeat. Requires 4-byte aligned request rows with req_pitch % 4 == 0 and
+ * ceil(n/8) % 4 == 0, and 16-byte aligned response rows with
+ * resp_pitch % 16 == 0 and d * msg_bytes % 16 == 0 (PIR_EINVAL otherwise).
+ * (Section "Evaluation": read requests are batched and forwarded to the GPU;
+ * the leader may reorder reads.)
  */
 int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req_pitch,
                           const uint32_t *sizes, const uint64_t *req_first, uint32_t n_batches,
@@ -165,8 +166,12 @@ enum pir_kernel_kind {
  * workgroup stream the same 1 KiB column chunk of D and take four
  * consecutive request tiles, so the chunk is read from L2 once per
  * workgroup instead of once per wave. Bits 8..11 (M4R_WIDE): how many
- * bucket groups ahead D is loaded (0 = 2). */
-enum { PIR_PLAN_SHARED_COLUMN = 1 };
+ * bucket groups ahead D is loaded (0 = 2). ROLLING (M4R_WIDE): table
+ * lookups keep a fixed number of LDS reads in flight and the next group's
+ * request offsets are fetched during the current one. SINGLE_TABLE
+ * (M4R_WIDE, implies rolling lookups): one table buffer per workgroup
+ * instead of two, so two workgroups share a CU. */
+enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12, PIR_PLAN_SINGLE_TABLE = 1 << 13 };
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
  * splits (0 = heuristic), unroll (MASK/SKIP: buckets loaded ahead; M4R:
@@ -217,7 +222,9 @@ int pir_profile_collect(pir_db *db, float *ms, uint32_t cap, uint32_t *count);
 /*
  * Configure the global interest vector (section "Private Notifications"):
  * m_bits Bloom-filter bits, union over the deltas of the last window_epochs
- * published epochs. Resets the vector. Defaults: 2^20 bits, 8 epochs.
+ * published epochs. Resets the vector. Defaults: 2^17 bits (16 KiB) and 100
+ * epochs, the paper's vector size at 1M messages and its TTL of 100 write
+ * intervals (section "Evaluation", cost of operations).
  * PIR_EINVAL for m_bits == 0, m_bits > 2^32 or window_epochs == 0.
  */
 int pir_interest_config(pir_db *db, uint64_t m_bits, uint32_t window_epochs);

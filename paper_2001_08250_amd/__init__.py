@@ -25,7 +25,10 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "talek_pir.h")
 PIR_OK, PIR_EINVAL, PIR_ERANGE, PIR_ENOMEM, PIR_EDEVICE, PIR_EFULL, PIR_EBUSY = 0, -1, -2, -3, -4, -5, -6
 KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R, KERNEL_M4R_WIDE = 0, 1, 2, 3, 4
 PLAN_SHARED_COLUMN = 1
+PLAN_ROLLING = 1 << 12
+PLAN_SINGLE_TABLE = 1 << 13
 PROFILE_MAX = 4096
+IV_DEFAULT_BITS, IV_DEFAULT_WINDOW = 1 << 17, 100   # the library's interest-vector defaults
 
 
 class PirError(RuntimeError):
@@ -294,7 +297,7 @@ class PirDB:
         return p, us.value
 
     # interest vector --------------------------------------------------------
-    def interest_config(self, m_bits: int = 1 << 20, window: int = 8):
+    def interest_config(self, m_bits: int = IV_DEFAULT_BITS, window: int = IV_DEFAULT_WINDOW):
         _check(self._L.pir_interest_config(self.h, m_bits, window), "pir_interest_config")
         self.m_bits = m_bits
 
@@ -303,7 +306,7 @@ class PirDB:
         _check(self._L.pir_interest_add(self.h, _ptr(pos, ctypes.c_uint32), pos.size), "pir_interest_add")
 
     def interest_vector(self) -> np.ndarray:
-        m = getattr(self, "m_bits", 1 << 20)
+        m = getattr(self, "m_bits", IV_DEFAULT_BITS)
         out = np.zeros((m + 7) // 8, dtype=np.uint8)
         _check(self._L.pir_interest_vector(self.h, _ptr(out), out.size), "pir_interest_vector")
         return out

@@ -10,6 +10,8 @@
 // vector is the OR of the last `window` deltas.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "engine.h"
 
 namespace talek {
@@ -47,14 +49,36 @@ __global__ __launch_bounds__(WG) void set_bits_kernel(uint32_t *__restrict__ wor
     atomicOr(words + (p >> 5), 1u << (p & 31u));
 }
 
-__global__ __launch_bounds__(WG) void or_rows_kernel(uint32_t *__restrict__ out, const uint32_t *__restrict__ rows,
-                                                     uint32_t nrows, uint64_t words)
+// out[i] = OR over r < nrows of rows[r * words + i], then row clear_row is
+// zeroed. A workgroup takes 64 consecutive words; its four waves OR
+// interleaved quarters of the rows (64 consecutive words per load, several
+// loads in flight) and combine them through LDS. Each (row, word) is read by
+// one thread only, which also clears it when it belongs to clear_row.
+__global__ __launch_bounds__(WG) void or_rows_kernel(uint32_t *__restrict__ out, uint32_t *__restrict__ rows,
+                                                     uint32_t nrows, uint64_t words, uint32_t clear_row)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < words; i += (uint64_t)gridDim.x * WG) {
+    __shared__ uint32_t part[WG / 64][64];
+    const uint32_t lane = threadIdx.x & 63u, sl = threadIdx.x >> 6;
+    for (uint64_t base = (uint64_t)blockIdx.x * 64; base < words; base += (uint64_t)gridDim.x * 64) {
+        const uint64_t i = base + lane;
         uint32_t v = 0;
-        for (uint32_t r = 0; r < nrows; ++r)
-            v |= rows[(uint64_t)r * words + i];
-        out[i] = v;
+        if (i < words) {
+#pragma unroll 4
+            for (uint32_t r = sl; r < nrows; r += WG / 64)
+                v |= rows[(uint64_t)r * words + i];
+            if (clear_row < nrows && clear_row % (WG / 64) == sl)
+                rows[(uint64_t)clear_row * words + i] = 0u;
+        }
+        part[sl][lane] = v;
+        __syncthreads();
+        if (sl == 0 && i < words) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < WG / 64; ++k)
+                o |= part[k][lane];
+            out[i] = o;
+        }
+        __syncthreads();
     }
 }
 
@@ -140,6 +164,20 @@ __global__ __launch_bounds__(WG) void gather_rows_kernel(uint4 *__restrict__ dst
         d[c] = s[c];
 }
 
+// dst row (dst_rows ? dst_rows[i] : i) = src row (src_rows ? src_rows[i] : i),
+// row_w 32-bit words per row; workgroup i copies row i.
+__global__ __launch_bounds__(WG) void move_rows_kernel(uint32_t *__restrict__ dst, uint64_t dst_pitch_w,
+                                                       const uint64_t *__restrict__ dst_rows,
+                                                       const uint32_t *__restrict__ src, uint64_t src_pitch_w,
+                                                       const uint64_t *__restrict__ src_rows, uint64_t row_w)
+{
+    const uint64_t i = blockIdx.x;
+    const uint32_t *s = src + (src_rows ? src_rows[i] : i) * src_pitch_w;
+    uint32_t *d = dst + (dst_rows ? dst_rows[i] : i) * dst_pitch_w;
+    for (uint64_t c = threadIdx.x; c < row_w; c += WG)
+        d[c] = s[c];
+}
+
 uint32_t grid_for(uint64_t items)
 {
     uint64_t g = (items + WG - 1) / WG;
@@ -149,6 +187,20 @@ uint32_t grid_for(uint64_t items)
 }
 
 }  // namespace
+
+hipError_t launch_move_rows(void *dst, uint64_t dst_pitch, const uint64_t *dst_rows, const void *src,
+                            uint64_t src_pitch, const uint64_t *src_rows, uint64_t count, uint64_t row_bytes,
+                            hipStream_t stream)
+{
+    if (count == 0)
+        return hipSuccess;
+    if (count > 0x7fffffffull || (dst_pitch & 3) || (src_pitch & 3) || (row_bytes & 3))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(move_rows_kernel, dim3((uint32_t)count), dim3(WG), 0, stream, static_cast<uint32_t *>(dst),
+                       dst_pitch / 4, dst_rows, static_cast<const uint32_t *>(src), src_pitch / 4, src_rows,
+                       row_bytes / 4);
+    return hipGetLastError();
+}
 
 hipError_t launch_scatter_rows(void *dst, const void *src, const uint64_t *idx, uint64_t count, uint64_t stride,
                                hipStream_t stream)
@@ -224,11 +276,14 @@ hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count,
     return hipGetLastError();
 }
 
-hipError_t launch_or_rows(uint32_t *out, const uint32_t *rows, uint32_t nrows, uint64_t words, hipStream_t stream)
+hipError_t launch_or_rows(uint32_t *out, uint32_t *rows, uint32_t nrows, uint64_t words, uint32_t clear_row,
+                          hipStream_t stream)
 {
     if (words == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(or_rows_kernel, dim3(grid_for(words)), dim3(WG), 0, stream, out, rows, nrows, words);
+    const uint64_t chunks = (words + 63) / 64;
+    hipLaunchKernelGGL(or_rows_kernel, dim3((uint32_t)std::min<uint64_t>(chunks, 65536)), dim3(WG), 0, stream, out,
+                       rows, nrows, words, clear_row);
     return hipGetLastError();
 }
 

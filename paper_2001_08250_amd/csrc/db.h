@@ -62,16 +62,15 @@ struct pir_db {
     // events recorded after async reads, per buffer and per stream
     std::map<hipStream_t, hipEvent_t> readers[2];
 
-    // staged bucket writes (pinned host rows, `stride` bytes each)
+    // staged bucket writes (mapped pinned host rows, `stride` bytes each;
+    // the commit kernels read them in place through the *_map pointers)
     uint8_t *stage_host = nullptr;
     uint64_t *stage_idx_host = nullptr;
+    void *stage_map = nullptr;
+    void *stage_idx_map = nullptr;
     uint64_t stage_cap = 0;   // rows
     uint64_t stage_rows = 0;
     std::unordered_map<uint64_t, uint64_t> stage_slot;
-    void *stage_dev = nullptr;
-    uint64_t stage_dev_cap = 0;
-    void *stage_idx_dev = nullptr;
-    uint64_t stage_idx_dev_cap = 0;
     // buckets changed in the open epoch
     std::vector<uint8_t> dirty_mark;
     std::vector<uint64_t> dirty;
@@ -87,17 +86,17 @@ struct pir_db {
     uint32_t *iv_ring = nullptr;       // window x iv_words
     uint32_t *iv_global[2] = {nullptr, nullptr};
     std::vector<uint32_t> pos_pending;
-    void *pos_dev = nullptr;
-    uint64_t pos_dev_cap = 0;
-    uint32_t *pos_host = nullptr;      // pinned
+    uint32_t *pos_host = nullptr;      // mapped pinned
+    void *pos_map = nullptr;
     uint64_t pos_host_cap = 0;
 
-    // Each pinned upload buffer is free for the host again once its event
-    // (recorded after the copy that reads it) has completed: 0 = staged rows
-    // and indices, 1 = interest positions, 2 = mirror indices.
+    // Each mapped pinned buffer is free for the host again once its event
+    // (recorded after the kernel that reads it) has completed: 0 = staged
+    // rows and indices, 1 = interest positions, 2 = mirror indices.
     hipEvent_t upload_ev[3] = {nullptr, nullptr, nullptr};
     bool upload_pending[3] = {false, false, false};
-    uint64_t *mirror_idx_host = nullptr;  // pinned
+    uint64_t *mirror_idx_host = nullptr;  // mapped pinned
+    void *mirror_map = nullptr;
     // kernel timing (pir_profile_*): event pairs, created on first use
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;

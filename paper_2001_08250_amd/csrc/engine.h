@@ -41,6 +41,8 @@ struct Plan {
     uint32_t flags;    // PLAN_SHARED_COLUMN
 };
 constexpr uint32_t PLAN_SHARED_COLUMN = 1;
+constexpr uint32_t PLAN_ROLLING = 1u << 12;
+constexpr uint32_t PLAN_SINGLE_TABLE = 1u << 13;
 
 // Device scratch the read needs for split partials: bytes.
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p);
@@ -80,51 +82,22 @@ hipError_t launch_stage_group_offsets(const void *Q, uint64_t qpitch, uint32_t B
 
 // dst row i = src row rows[i], i < count; pitches multiples of 16, rows of
 // round_up(row_bytes, 16) bytes are copied. src and rows may be host-mapped.
+// Row copy: dst row (dst_rows ? dst_rows[i] : i) = src row (src_rows ?
+// src_rows[i] : i) for i < count, row_bytes bytes each (multiple of 4; rows
+// and pitches 4-byte aligned). One workgroup per row.
+hipError_t launch_move_rows(void *dst, uint64_t dst_pitch, const uint64_t *dst_rows, const void *src,
+                            uint64_t src_pitch, const uint64_t *src_rows, uint64_t count, uint64_t row_bytes,
+                            hipStream_t stream);
 hipError_t launch_gather_rows(void *dst, uint64_t dst_pitch, const void *src, uint64_t src_pitch,
                               const uint32_t *rows, uint32_t count, uint64_t row_bytes, hipStream_t stream);
 
 // --- interest vector -----------------------------------------------------
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);           // bytes % 4 == 0
 hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count, hipStream_t stream);
-hipError_t launch_or_rows(uint32_t *out, const uint32_t *rows, uint32_t nrows, uint64_t words,
+// out = OR of the nrows rows of `words` words; row clear_row (< nrows, or
+// none) is zeroed after it has been read.
+hipError_t launch_or_rows(uint32_t *out, uint32_t *rows, uint32_t nrows, uint64_t words, uint32_t clear_row,
                           hipStream_t stream);
 
-// --- persistent work-queue read (uneven batch streams) ------------------
-struct QueueItem {       // one work item: 16 bytes
-    uint32_t batch;      // index into the batch table
-    uint32_t rt;         // request tile within the batch
-    uint32_t s;          // bucket split
-    uint32_t cg;         // column group (1 KiB x 4 waves)
-};
-struct QueueBatch {      // per batch: 64 bytes (same layout on host and device)
-    uint64_t q_off;      // byte offset of the batch's first request row
-    uint64_t out_off;    // byte offset of the batch's first response row
-    uint64_t part_off;   // byte offset of the batch's partial buffer
-    uint32_t B;
-    uint32_t splits;
-    uint32_t words_per_split;
-    uint32_t n_rt;
-    uint32_t n_cg;
-    uint32_t group_base; // first completion counter of this batch
-    uint32_t pad[4];
-};
-struct QueueGeom {
-    const void *D;
-    uint64_t n;
-    uint64_t stride;
-    const void *Q;       // base of all batches' request rows
-    uint64_t qpitch;
-    void *out;           // base of all batches' response rows
-    uint64_t out_pitch;
-    void *partials;      // base of all batches' partial buffers
-    const QueueItem *items;
-    const QueueBatch *batches;
-    uint32_t *head;      // work counter, zero before launch
-    uint32_t *done;      // completion counters, zero before launch
-    uint32_t n_items;
-};
-constexpr uint32_t QUEUE_TILE = 16;   // requests per wave in the queue kernel
-hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream);
-uint32_t queue_grid(int num_cus);
 
 }  // namespace talek

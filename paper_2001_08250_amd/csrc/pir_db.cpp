@@ -124,6 +124,24 @@ int ensure_back(pir_db *db)
 
 enum { UP_STAGE = 0, UP_POS = 1, UP_MIRROR = 2 };
 
+// Pinned host memory that kernels read in place: *host for the CPU, *dev
+// for kernels.
+int host_mapped(uint64_t bytes, void **host, void **dev)
+{
+    *host = *dev = nullptr;
+    if (hipHostMalloc(host, std::max<uint64_t>(bytes, 64), hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        *host = nullptr;
+        return PIR_ENOMEM;
+    }
+    if (hipHostGetDevicePointer(dev, *host, 0) != hipSuccess) {
+        hipHostFree(*host);
+        *host = nullptr;
+        return PIR_EDEVICE;
+    }
+    return PIR_OK;
+}
+
 // Block until pinned upload buffer `which` is no longer read by a queued copy.
 int wait_upload(pir_db *db, int which)
 {
@@ -149,19 +167,15 @@ void mark_dirty(pir_db *db, uint64_t b)
     db->dirty.push_back(b);
 }
 
-// Apply the staged rows to the back copy; afterwards the staging is empty.
+// Apply the staged rows to the back copy (the kernel reads them straight
+// from mapped host memory); afterwards the staging is empty.
 int flush_stage(pir_db *db)
 {
     if (db->stage_rows == 0)
         return PIR_OK;
     PIR_TRY(ensure_back(db));
     const uint64_t rows = db->stage_rows;
-    PIR_TRY(ensure_device(&db->stage_dev, &db->stage_dev_cap, rows * db->stride));
-    PIR_TRY(ensure_device(&db->stage_idx_dev, &db->stage_idx_dev_cap, rows * sizeof(uint64_t)));
-    HIP_TRY(hipMemcpyAsync(db->stage_dev, db->stage_host, rows * db->stride, hipMemcpyHostToDevice, db->stream));
-    HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->stage_idx_host, rows * sizeof(uint64_t), hipMemcpyHostToDevice,
-                           db->stream));
-    HIP_TRY(launch_scatter_rows(db->buf[db->front ^ 1], db->stage_dev, static_cast<uint64_t *>(db->stage_idx_dev),
+    HIP_TRY(launch_scatter_rows(db->buf[db->front ^ 1], db->stage_map, static_cast<const uint64_t *>(db->stage_idx_map),
                                 rows, db->stride, db->stream));
     PIR_TRY(note_upload(db, UP_STAGE));  // the staging rows are refilled only after this
     for (uint64_t i = 0; i < rows; ++i)
@@ -246,9 +260,6 @@ void free_db(pir_db *db)
         hipFree(db->iv_global[b]);
     }
     hipFree(db->iv_ring);
-    hipFree(db->stage_dev);
-    hipFree(db->stage_idx_dev);
-    hipFree(db->pos_dev);
     if (db->stage_host)
         hipHostFree(db->stage_host);
     if (db->stage_idx_host)
@@ -339,15 +350,16 @@ int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
             break;
         }
         db->stage_cap = std::max<uint64_t>(1, std::min<uint64_t>(n, STAGE_BYTES / stride));
-        if (hipHostMalloc(&p, db->stage_cap * stride, hipHostMallocDefault) != hipSuccess) { rc = PIR_ENOMEM; break; }
-        db->stage_host = static_cast<uint8_t *>(p);
-        if (hipHostMalloc(&p, db->stage_cap * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
-            rc = PIR_ENOMEM;
+        if ((rc = host_mapped(db->stage_cap * stride, &p, &db->stage_map)) != PIR_OK)
             break;
-        }
+        db->stage_host = static_cast<uint8_t *>(p);
+        if ((rc = host_mapped(db->stage_cap * sizeof(uint64_t), &p, &db->stage_idx_map)) != PIR_OK)
+            break;
         db->stage_idx_host = static_cast<uint64_t *>(p);
         db->dirty_mark.assign(n, 0);
-        if ((rc = interest_alloc(db, 1ull << 20, 8)) != PIR_OK)
+        // the paper's sizes: a vector of about 14 KB at 1M messages and a TTL
+        // of 100 write intervals (section "Evaluation", cost of operations)
+        if ((rc = interest_alloc(db, 1ull << 17, 100)) != PIR_OK)
             break;
         if (hipEventRecord(db->published, db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
         if (hipStreamSynchronize(db->stream) != hipSuccess) { rc = PIR_EDEVICE; break; }
@@ -435,32 +447,33 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 
     // interest vector: the open epoch's delta replaces the oldest ring slot;
     // the new global vector (OR of the window) goes with the back copy.
+    // The ring slot of this epoch is all zero (cleared by the previous
+    // commit's OR, or at configuration); the positions are read in place
+    // from mapped host memory.
     PIR_TRY(wait_upload(db, UP_POS));
-    if (db->pos_pending.size() > db->pos_host_cap) {
+    const uint64_t npos = db->pos_pending.size();
+    if (npos > db->pos_host_cap) {
         if (db->pos_host)
             hipHostFree(db->pos_host);
         db->pos_host = nullptr;
         db->pos_host_cap = 0;
         void *p = nullptr;
-        if (hipHostMalloc(&p, db->pos_pending.size() * 4, hipHostMallocDefault) != hipSuccess)
-            return PIR_ENOMEM;
+        PIR_TRY(host_mapped(npos * 4, &p, &db->pos_map));
         db->pos_host = static_cast<uint32_t *>(p);
-        db->pos_host_cap = db->pos_pending.size();
+        db->pos_host_cap = npos;
     }
-    const uint64_t npos = db->pos_pending.size();
+    uint32_t *slot = db->iv_ring + (db->epoch % db->window) * db->iv_words;
     if (npos) {
         memcpy(db->pos_host, db->pos_pending.data(), npos * 4);
-        PIR_TRY(ensure_device(&db->pos_dev, &db->pos_dev_cap, npos * 4));
-        HIP_TRY(hipMemcpyAsync(db->pos_dev, db->pos_host, npos * 4, hipMemcpyHostToDevice, db->stream));
+        HIP_TRY(launch_set_bits(slot, static_cast<const uint32_t *>(db->pos_map), npos, db->stream));
         PIR_TRY(note_upload(db, UP_POS));
     }
     // The back copy's vector may still be read by async readers of the
-    // buffer it belonged to before the last swap.
+    // buffer it belonged to before the last swap. The OR also clears the
+    // slot of the oldest epoch of this window, which the next commit fills.
     PIR_TRY(wait_readers(db, back, db->stream));
-    uint32_t *slot = db->iv_ring + (db->epoch % db->window) * db->iv_words;
-    HIP_TRY(launch_fill_zero(slot, db->iv_words * 4, db->stream));
-    HIP_TRY(launch_set_bits(slot, static_cast<uint32_t *>(db->pos_dev), npos, db->stream));
-    HIP_TRY(launch_or_rows(db->iv_global[back], db->iv_ring, db->window, db->iv_words, db->stream));
+    HIP_TRY(launch_or_rows(db->iv_global[back], db->iv_ring, db->window, db->iv_words,
+                           (uint32_t)((db->epoch + 1) % db->window), db->stream));
     db->pos_pending.clear();
 
     if (changed) {
@@ -496,18 +509,14 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
             db->mirror_idx_host = nullptr;
             db->mirror_idx_cap = 0;
             void *p = nullptr;
-            if (hipHostMalloc(&p, cnt * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
-                return PIR_ENOMEM;
+            PIR_TRY(host_mapped(cnt * sizeof(uint64_t), &p, &db->mirror_map));
             db->mirror_idx_host = static_cast<uint64_t *>(p);
             db->mirror_idx_cap = cnt;
         }
         memcpy(db->mirror_idx_host, db->dirty.data(), cnt * sizeof(uint64_t));
-        PIR_TRY(ensure_device(&db->stage_idx_dev, &db->stage_idx_dev_cap, cnt * sizeof(uint64_t)));
-        HIP_TRY(hipMemcpyAsync(db->stage_idx_dev, db->mirror_idx_host, cnt * sizeof(uint64_t),
-                               hipMemcpyHostToDevice, db->stream));
-        PIR_TRY(note_upload(db, UP_MIRROR));
         HIP_TRY(launch_copy_rows(db->buf[old_front], db->buf[db->front],
-                                 static_cast<uint64_t *>(db->stage_idx_dev), cnt, db->stride, db->stream));
+                                 static_cast<const uint64_t *>(db->mirror_map), cnt, db->stride, db->stream));
+        PIR_TRY(note_upload(db, UP_MIRROR));
     }
     // no host wait: the rest of the commit runs stream-ordered on the device
     for (uint64_t b : db->dirty)

@@ -56,8 +56,20 @@ uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
 Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
-    if (p.kind == KIND_AUTO)
-        p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
+    if (p.kind == KIND_AUTO) {
+        // Small batches stream D with the plain tile kernels; from about
+        // 160 requests on, 64 KiB Four-Russians tables shared by 256
+        // requests per workgroup cost less than per-request XORs (below
+        // that the table builds dominate).
+        if (g.B >= 160) {
+            p.kind = KIND_M4RW;
+            p.flags = PLAN_ROLLING;
+            p.unroll = 8;
+            p.tile = 32;
+        } else {
+            p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
+        }
+    }
     const uint64_t nwords = (g.n + 31) / 32;
     const uint32_t stride16 = (uint32_t)(g.stride / 16);
     uint64_t units;  // independent workgroup tasks per split
@@ -76,7 +88,9 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         if (p.unroll == 0)
             p.unroll = 8;
         units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
-        per_cu = 2;
+        // two 64 KiB tables fill a CU's LDS; a single table leaves room for a
+        // second workgroup
+        per_cu = (p.flags & PLAN_SINGLE_TABLE) ? 2 : 1;
     } else {
         if (p.tile == 0)
             p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;

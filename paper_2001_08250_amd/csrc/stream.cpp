@@ -1,7 +1,15 @@
-// Uneven batch streams through the persistent work-queue kernel, captured in
-// a HIP graph and replayed while the stream shape, buffers and snapshot stay
-// the same (section "Evaluation": reads are batched and forwarded to the GPU;
-// the leader may reorder reads).
+// Uneven batch streams (section "Evaluation": read requests are batched and
+// forwarded to the GPU; the leader may reorder reads).
+//
+// Every answer depends only on its own request row and the snapshot, so the
+// stream's rows, in order, are cut into launch groups of FUSE_ROWS requests
+// (a batch may straddle two groups; the last group takes the rest): one read
+// launch per group, with that size's tuned schedule. Full groups keep every
+// request tile of the Four-Russians kernel full, and each launch streams the
+// database once however many batches it serves. Request rows that are not contiguous are gathered into scratch
+// first; response rows that are not contiguous are scattered from scratch
+// afterwards. The launch sequence is captured in a HIP graph and replayed
+// while the stream shape, buffers and snapshot stay the same.
 #include <string.h>
 
 #include <algorithm>
@@ -13,24 +21,17 @@ using namespace talek;
 
 namespace {
 
-constexpr uint64_t CHUNK_PARTIAL_BYTES = 256ull << 20;
+constexpr uint32_t FUSE_ROWS = 1024;  // requests per launch group
 
-struct Chunk {
-    uint32_t first_batch, n_batches;
-    uint32_t first_item, n_items;
-    uint32_t n_groups;
-    uint64_t part_bytes;
+struct Group {
+    uint32_t B;
+    uint64_t req_row;    // first request row when contiguous
+    uint64_t resp_row;   // first response row when contiguous
+    bool gather;         // request rows need gathering
+    bool scatter;        // response rows need scattering
+    uint64_t idx_req;    // offsets (in rows) into the uploaded index lists
+    uint64_t idx_resp;
 };
-
-uint32_t batch_splits(uint64_t n, uint32_t B, uint32_t n_cg, int num_cus)
-{
-    const uint64_t n_rt = (B + QUEUE_TILE - 1) / QUEUE_TILE;
-    const uint64_t units = n_rt * n_cg;
-    const uint64_t nwords = (n + 31) / 32;
-    uint64_t s = (2ull * std::max(num_cus, 1) + units - 1) / units;
-    s = std::min<uint64_t>(s, std::max<uint64_t>(nwords / 2, 1));
-    return (uint32_t)std::max<uint64_t>(s, 1);
-}
 
 }  // namespace
 
@@ -55,81 +56,101 @@ extern "C" int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req
     if (hipSetDevice(db->device) != hipSuccess)
         return PIR_EDEVICE;
 
-    const uint32_t stride16 = (uint32_t)(db->stride / 16);
-    const uint32_t n_cg = (stride16 + 255) / 256;
-    const uint64_t nwords = (db->n + 31) / 32;
-
-    // Work tables for all chunks.
-    std::vector<QueueBatch> batches(n_batches);
-    std::vector<QueueItem> items;
-    std::vector<Chunk> chunks;
-    uint64_t req_row = 0, resp_row = 0;
-    Chunk cur{0, 0, 0, 0, 0, 0};
-    uint64_t max_part = 0;
-    for (uint32_t k = 0; k < n_batches; ++k) {
-        const uint32_t B = sizes[k];
-        QueueBatch &bt = batches[k];
-        memset(&bt, 0, sizeof bt);
-        const uint64_t rq = req_first ? req_first[k] : req_row;
-        const uint64_t rs = resp_first ? resp_first[k] : resp_row;
-        req_row = rq + B;
-        resp_row = rs + B;
-        bt.q_off = rq * req_pitch;
-        bt.out_off = rs * resp_pitch;
-        bt.B = B;
-        if (B == 0)
-            continue;
-        bt.n_cg = n_cg;
-        bt.n_rt = (B + QUEUE_TILE - 1) / QUEUE_TILE;
-        bt.splits = batch_splits(db->n, B, n_cg, db->num_cus);
-        bt.words_per_split = (uint32_t)((nwords + bt.splits - 1) / bt.splits);
-        bt.splits = (uint32_t)((nwords + bt.words_per_split - 1) / bt.words_per_split);
-        const uint64_t part = bt.splits > 1 ? (uint64_t)bt.splits * B * db->stride : 0;
-        if (cur.n_batches && cur.part_bytes + part > CHUNK_PARTIAL_BYTES) {
-            chunks.push_back(cur);
-            cur = Chunk{k, 0, (uint32_t)items.size(), 0, 0, 0};
+    // Absolute first rows of every batch.
+    std::vector<uint64_t> rq(n_batches), rs(n_batches);
+    {
+        uint64_t a = 0, b = 0;
+        for (uint32_t k = 0; k < n_batches; ++k) {
+            rq[k] = req_first ? req_first[k] : a;
+            rs[k] = resp_first ? resp_first[k] : b;
+            a = rq[k] + sizes[k];
+            b = rs[k] + sizes[k];
         }
-        if (cur.n_batches == 0) {
-            cur.first_batch = k;
-            cur.first_item = (uint32_t)items.size();
-        }
-        bt.part_off = cur.part_bytes;
-        bt.group_base = cur.n_groups;
-        cur.part_bytes += part;
-        cur.n_groups += bt.splits > 1 ? bt.n_rt * n_cg : 0;
-        for (uint32_t sp = 0; sp < bt.splits; ++sp)
-            for (uint32_t cg = 0; cg < n_cg; ++cg)
-                for (uint32_t rt = 0; rt < bt.n_rt; ++rt)
-                    items.push_back(QueueItem{k, rt, sp, cg});
-        cur.n_batches = k + 1 - cur.first_batch;
-        cur.n_items = (uint32_t)items.size() - cur.first_item;
-        max_part = std::max(max_part, cur.part_bytes);
     }
-    if (cur.n_batches)
-        chunks.push_back(cur);
-    if (items.empty())
+
+    // Launch groups, and the row index lists of the groups whose rows are
+    // not contiguous.
+    std::vector<Group> groups;
+    std::vector<uint64_t> idx;
+    struct Seg {
+        uint32_t k, i0, cnt;  // rows i0 .. i0 + cnt - 1 of batch k
+    };
+    std::vector<Seg> segs;
+    uint32_t k = 0, i0 = 0;
+    while (k < n_batches) {
+        Group gr{0, 0, 0, false, false, 0, 0};
+        segs.clear();
+        while (k < n_batches && gr.B < FUSE_ROWS) {
+            const uint32_t left = sizes[k] - i0;
+            if (left == 0) {
+                ++k;
+                i0 = 0;
+                continue;
+            }
+            const uint32_t c = std::min<uint32_t>(left, FUSE_ROWS - gr.B);
+            const uint64_t q = rq[k] + i0, r = rs[k] + i0;
+            if (gr.B == 0) {
+                gr.req_row = q;
+                gr.resp_row = r;
+            } else {
+                gr.gather |= q != gr.req_row + gr.B;
+                gr.scatter |= r != gr.resp_row + gr.B;
+            }
+            segs.push_back(Seg{k, i0, c});
+            gr.B += c;
+            i0 += c;
+        }
+        if (gr.B == 0)
+            continue;
+        if (gr.gather || gr.scatter) {
+            gr.idx_req = idx.size();
+            for (const Seg &sg : segs)
+                for (uint32_t i = 0; i < sg.cnt; ++i)
+                    idx.push_back(rq[sg.k] + sg.i0 + i);
+            gr.idx_resp = idx.size();
+            for (const Seg &sg : segs)
+                for (uint32_t i = 0; i < sg.cnt; ++i)
+                    idx.push_back(rs[sg.k] + sg.i0 + i);
+        }
+        groups.push_back(gr);
+    }
+    if (groups.empty())
         return PIR_OK;
 
+    // Scratch: index lists (aux), gathered requests, scattered responses and
+    // the largest schedule's partials / staging (part).
+    uint64_t req_rows = 0, resp_rows = 0, part = 16;
+    std::vector<Plan> plans(groups.size());
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const Group &gr = groups[i];
+        if (gr.gather)
+            req_rows = std::max<uint64_t>(req_rows, gr.B);
+        if (gr.scatter)
+            resp_rows = std::max<uint64_t>(resp_rows, gr.B);
+        plans[i] = choose_plan(db, gr.B);
+        ReadGeom g = read_geom(db, d_req, req_pitch, gr.B, d_resp, resp_pitch);
+        part = std::max<uint64_t>(part, partial_bytes(g, plans[i]));
+    }
+    const uint64_t idx_bytes = (idx.size() * 8 + 255) & ~255ull;
+    const uint64_t req_bytes = (req_rows * db->qpitch + 255) & ~255ull;
+    const uint64_t resp_bytes = resp_rows * db->stride;
     Scratch &sc = scratch_for(db, s);
-    const uint64_t batch_bytes = batches.size() * sizeof(QueueBatch);
-    const uint64_t item_bytes = items.size() * sizeof(QueueItem);
-    uint64_t counter_words = 0;
-    for (const Chunk &c : chunks)
-        counter_words += 1 + c.n_groups;
-    const uint64_t aux_bytes = batch_bytes + item_bytes + counter_words * 4;
-
     void *old_aux = sc.aux, *old_part = sc.part;
-    int rc = ensure_device(&sc.aux, &sc.aux_cap, aux_bytes);
+    int rc = ensure_device(&sc.aux, &sc.aux_cap, std::max<uint64_t>(idx_bytes + req_bytes + resp_bytes, 16));
     if (rc == PIR_OK)
-        rc = ensure_device(&sc.part, &sc.part_cap, std::max<uint64_t>(max_part, 16));
+        rc = ensure_device(&sc.part, &sc.part_cap, part);
     if (rc != PIR_OK)
         return rc;
     if (sc.aux != old_aux || sc.part != old_part)
         destroy_stream_graph(sc);
+    uint8_t *aux = static_cast<uint8_t *>(sc.aux);
+    const uint64_t *d_idx = reinterpret_cast<const uint64_t *>(aux);
+    uint8_t *req_scratch = aux + idx_bytes;
+    uint8_t *resp_scratch = aux + idx_bytes + req_bytes;
 
     // Signature of everything the captured graph bakes in.
     std::vector<uint64_t> sig;
-    sig.reserve(8 + 2 * n_batches);
+    sig.reserve(8 + 4 * groups.size() + idx.size());
     sig.push_back(reinterpret_cast<uintptr_t>(db->buf[db->front]));
     sig.push_back(reinterpret_cast<uintptr_t>(d_req));
     sig.push_back(req_pitch);
@@ -137,10 +158,16 @@ extern "C" int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req
     sig.push_back(resp_pitch);
     sig.push_back(reinterpret_cast<uintptr_t>(sc.aux));
     sig.push_back(reinterpret_cast<uintptr_t>(sc.part));
-    for (uint32_t k = 0; k < n_batches; ++k) {
-        sig.push_back(((uint64_t)batches[k].B << 32) ^ batches[k].q_off);
-        sig.push_back(batches[k].out_off);
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const Group &gr = groups[i];
+        const Plan &p = plans[i];
+        sig.push_back(((uint64_t)gr.B << 32) | (gr.gather ? 2u : 0u) | (gr.scatter ? 1u : 0u));
+        sig.push_back(gr.req_row);
+        sig.push_back(gr.resp_row);
+        sig.push_back(((uint64_t)p.kind << 56) ^ ((uint64_t)p.tile << 40) ^ ((uint64_t)p.unroll << 32) ^
+                      ((uint64_t)p.flags << 16) ^ p.splits);
     }
+    sig.insert(sig.end(), idx.begin(), idx.end());
 
     if (hipStreamWaitEvent(s, db->published, 0) != hipSuccess)
         return PIR_EDEVICE;
@@ -151,47 +178,37 @@ extern "C" int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req
     }
     destroy_stream_graph(sc);
 
-    // Upload the tables (stream-ordered on s, before the graph runs).
-    std::vector<uint8_t> host(aux_bytes, 0);
-    memcpy(host.data(), batches.data(), batch_bytes);
-    memcpy(host.data() + batch_bytes, items.data(), item_bytes);
-    if (hipMemcpyAsync(sc.aux, host.data(), aux_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-        return PIR_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess)  // host table is a temporary
-        return PIR_EDEVICE;
-
-    uint8_t *aux = static_cast<uint8_t *>(sc.aux);
-    const QueueBatch *d_batches = reinterpret_cast<const QueueBatch *>(aux);
-    const QueueItem *d_items = reinterpret_cast<const QueueItem *>(aux + batch_bytes);
-    uint32_t *d_counters = reinterpret_cast<uint32_t *>(aux + batch_bytes + item_bytes);
+    if (!idx.empty()) {  // index lists, stream-ordered before the graph runs
+        if (hipMemcpyAsync(sc.aux, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)  // idx is a temporary
+            return PIR_EDEVICE;
+    }
 
     hipStream_t cap = db->capture_stream;
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return PIR_EDEVICE;
     hipError_t e = hipSuccess;
-    uint64_t cw = 0;
-    const uint32_t grid = queue_grid(db->num_cus);
-    for (const Chunk &c : chunks) {
-        uint32_t *counters = d_counters + cw;
-        cw += 1 + c.n_groups;
+    for (size_t i = 0; i < groups.size() && e == hipSuccess; ++i) {
+        const Group &gr = groups[i];
+        const void *q = static_cast<const uint8_t *>(d_req) + gr.req_row * req_pitch;
+        uint64_t qp = req_pitch;
+        if (gr.gather) {
+            e = launch_move_rows(req_scratch, db->qpitch, nullptr, d_req, req_pitch, d_idx + gr.idx_req, gr.B,
+                                 db->qbytes, cap);
+            q = req_scratch;
+            qp = db->qpitch;
+        }
+        void *out = static_cast<uint8_t *>(d_resp) + gr.resp_row * resp_pitch;
+        uint64_t op = resp_pitch;
+        if (gr.scatter) {
+            out = resp_scratch;
+            op = db->stride;
+        }
         if (e == hipSuccess)
-            e = launch_fill_zero(counters, (1 + (uint64_t)c.n_groups) * 4, cap);
-        QueueGeom g{};
-        g.D = db->buf[db->front];
-        g.n = db->n;
-        g.stride = db->stride;
-        g.Q = d_req;
-        g.qpitch = req_pitch;
-        g.out = d_resp;
-        g.out_pitch = resp_pitch;
-        g.partials = sc.part;
-        g.items = d_items + c.first_item;
-        g.batches = d_batches;
-        g.head = counters;
-        g.done = counters + 1;
-        g.n_items = c.n_items;
-        if (e == hipSuccess)
-            e = launch_queue(g, std::min<uint32_t>(grid, c.n_items), cap);
+            e = launch_read(read_geom(db, q, qp, gr.B, out, op), plans[i], sc.part, cap);
+        if (e == hipSuccess && gr.scatter)
+            e = launch_move_rows(d_resp, resp_pitch, d_idx + gr.idx_resp, resp_scratch, db->stride, nullptr, gr.B,
+                                 db->bucket_bytes, cap);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cap, &graph);

@@ -114,6 +114,28 @@ __device__ __forceinline__ void lookup(uint4 (&acc)[TW], const uint8_t *tbl, con
     }
 }
 
+// Rolling lookups: INFL ds_read_b128 stay in flight; the buffer of request r
+// is refilled with request r + INFL right after its XOR, so LDS latency
+// overlaps the XORs of the requests before it.
+template <int TW, int INFL>
+__device__ __forceinline__ void lookup_rolling(uint4 (&acc)[TW], const uint8_t *tbl, const uint32_t (&off)[TW])
+{
+    uint4 t[INFL];
+#pragma unroll
+    for (int i = 0; i < INFL; ++i)
+        t[i] = *reinterpret_cast<const uint4 *>(tbl + off[i]);
+#pragma unroll
+    for (int r = 0; r < TW; ++r) {
+        // keep this order: the scheduler would otherwise cluster the reads
+        // back into batches
+        __builtin_amdgcn_sched_barrier(0);
+        xor4(acc[r], t[r % INFL]);
+        if (r + INFL < TW)
+            t[r % INFL] = *reinterpret_cast<const uint4 *>(tbl + off[r + INFL]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Group step for group x, K = (x - first group) mod U with U = lcm(P, 2):
 // ring[K % P] held group x (already built) and is refilled with group x + P,
 // so D loads run P - 1 steps ahead of their use; then group x + 1 (in
@@ -121,57 +143,105 @@ __device__ __forceinline__ void lookup(uint4 (&acc)[TW], const uint8_t *tbl, con
 // up from buffer K & 1, and the workgroup synchronises. Loads and builds past
 // the range are harmless (readable padding rows, a table nobody reads) and
 // keep the code straight-line so the waits stay exact.
-template <int NW, int TW, int P, int K>
-__device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
-                                           const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
-                                           uint64_t x, const uint32_t *__restrict__ q, bool active, uint32_t wave,
-                                           uint32_t lane)
+//
+// MODE 0: the group's TW offsets are read (scalar loads) at its lookup and
+// looked up in batches. MODE 1: offs already holds them (loaded at the end of
+// the previous step, so they landed in the wait that precedes the barrier);
+// lookups are rolling, and the next group's offsets are loaded after them
+// (the staging area has one zero group past the end). MODE 2: as MODE 1 with
+// a single table buffer: build, barrier, look up, barrier. Half the LDS, so
+// two workgroups share a CU and overlap one's table build with the other's
+// lookups.
+template <int NW, int TW, int P, int MODE, int K>
+__device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint32_t (&offs)[TW],
+                                           uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                           uint32_t lane_off, uint64_t x, const uint32_t *__restrict__ Qw,
+                                           uint32_t Bp, bool active, uint32_t wave, uint32_t lane)
 {
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
-    load_group(ring[slot], D, row_bytes, lane_off, x + P);
-    build_table<NW>(lds + (buf ^ 1) * TABLE_U4, ring[next], wave, lane);
-    if (active)
-        lookup<TW, (NW >= 16 ? 4 : 8)>(acc, reinterpret_cast<const uint8_t *>(lds + buf * TABLE_U4 + lane), q);
+    const uint32_t *q = Qw + x * Bp;
+    const uint8_t *tbl;
+    if constexpr (MODE == 2) {
+        // one table buffer: build group x (loaded P steps ago), refill its
+        // ring slot with group x + P, and let every wave finish the table
+        build_table<NW>(lds, ring[slot], wave, lane);
+        load_group(ring[slot], D, row_bytes, lane_off, x + P);
+        __syncthreads();
+        tbl = reinterpret_cast<const uint8_t *>(lds + lane);
+    } else {
+        load_group(ring[slot], D, row_bytes, lane_off, x + P);
+        build_table<NW>(lds + (buf ^ 1) * TABLE_U4, ring[next], wave, lane);
+        tbl = reinterpret_cast<const uint8_t *>(lds + buf * TABLE_U4 + lane);
+    }
+    if (active) {
+        if constexpr (MODE >= 1)
+            lookup_rolling<TW, (NW >= 16 || MODE == 2 ? 4 : 8)>(acc, tbl, offs);
+        else
+            lookup<TW, (NW >= 16 ? 4 : 8)>(acc, tbl, q);
+    }
+    if (MODE >= 1 && active) {
+        // Rows r0 .. r0 + TW - 1 < Bp (r0 < B, TW divides 64) of group
+        // x + 1 <= groups: inside the staging area. The group index goes
+        // through readfirstlane so loop strength reduction cannot split the
+        // TW addresses into separate induction pointers; they stay one base
+        // plus constant offsets (wide scalar loads).
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(x + 1));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((x + 1) >> 32));
+        const uint32_t *qn = Qw + (((uint64_t)hi << 32) | lo) * Bp;
+#pragma unroll
+        for (int i = 0; i < TW; ++i)
+            offs[i] = qn[i];
+    }
     __syncthreads();
 }
 
-template <int NW, int TW, int P, int K, int U>
-__device__ __forceinline__ void group_steps(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
-                                            const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
-                                            uint64_t x, const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
-                                            uint32_t wave, uint32_t lane)
+template <int NW, int TW, int P, int MODE, int K, int U>
+__device__ __forceinline__ void group_steps(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint32_t (&offs)[TW],
+                                            uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                            uint32_t lane_off, uint64_t x, const uint32_t *__restrict__ Qw,
+                                            uint32_t Bp, bool active, uint32_t wave, uint32_t lane)
 {
     if constexpr (K < U) {
-        group_step<NW, TW, P, K>(acc, ring, lds, D, row_bytes, lane_off, x + K, Qw + (x + K) * Bp, active, wave,
-                                 lane);
-        group_steps<NW, TW, P, K + 1, U>(acc, ring, lds, D, row_bytes, lane_off, x, Qw, Bp, active, wave, lane);
+        group_step<NW, TW, P, MODE, K>(acc, ring, offs, lds, D, row_bytes, lane_off, x + K, Qw, Bp,
+                                       active, wave, lane);
+        group_steps<NW, TW, P, MODE, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, x, Qw, Bp, active,
+                                               wave, lane);
     }
 }
 
 // Tail: the first `left` (< U) steps of an unrolled iteration.
-template <int NW, int TW, int P, int K, int U>
-__device__ __forceinline__ void group_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint4 *lds,
-                                                 const uint8_t *__restrict__ D, uint64_t row_bytes,
+template <int NW, int TW, int P, int MODE, int K, int U>
+__device__ __forceinline__ void group_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint32_t (&offs)[TW],
+                                                 uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
                                                  uint32_t lane_off, uint64_t x, uint64_t left,
                                                  const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
                                                  uint32_t wave, uint32_t lane)
 {
     if constexpr (K < U) {
         if ((uint64_t)K < left) {
-            group_step<NW, TW, P, K>(acc, ring, lds, D, row_bytes, lane_off, x + K, Qw + (x + K) * Bp, active,
-                                     wave, lane);
-            group_steps_tail<NW, TW, P, K + 1, U>(acc, ring, lds, D, row_bytes, lane_off, x, left, Qw, Bp, active,
-                                                  wave, lane);
+            group_step<NW, TW, P, MODE, K>(acc, ring, offs, lds, D, row_bytes, lane_off, x + K, Qw, Bp,
+                                           active, wave, lane);
+            group_steps_tail<NW, TW, P, MODE, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, x, left, Qw,
+                                                        Bp, active, wave, lane);
         }
     }
 }
 
-template <int NW, int TW, int P>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(1, NW / 4)))
+// Waves per SIMD to reserve registers for: one workgroup per CU, two in
+// MODE 2.
+template <int NW, int MODE>
+constexpr int waves_per_simd()
+{
+    return (MODE == 2 ? 2 : 1) * NW / 4;
+}
+
+template <int NW, int TW, int P, int MODE>
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<NW, MODE>(), waves_per_simd<NW, MODE>())))
 void xorpir_m4rw_kernel(const WideArgs a)
 {
     constexpr int U = (P % 2 == 0) ? P : 2 * P;  // lcm(P, 2)
-    __shared__ uint4 lds[2 * TABLE_U4];
+    __shared__ uint4 lds[(MODE == 2 ? 1 : 2) * TABLE_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
     if (t >= a.n_rt * a.slices * a.splits)
@@ -202,16 +272,24 @@ void xorpir_m4rw_kernel(const WideArgs a)
 #pragma unroll
         for (int k = 0; k < P; ++k)
             load_group(ring[k], a.D, a.row_bytes, lane_off, gb + k);
-        build_table<NW>(lds, ring[0], wave, lane);
-        __syncthreads();
         const uint32_t *Qw = a.Qs + r0;
+        uint32_t offs[TW] = {};
+        if (MODE >= 1 && active) {
+#pragma unroll
+            for (int i = 0; i < TW; ++i)
+                offs[i] = Qw[gb * a.Bp + i];
+        }
+        if constexpr (MODE != 2) {
+            build_table<NW>(lds, ring[0], wave, lane);
+            __syncthreads();
+        }
         uint64_t x = gb;
         for (; x + U <= ge; x += U)
-            group_steps<NW, TW, P, 0, U>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, Qw, a.Bp, active, wave,
-                                         lane);
+            group_steps<NW, TW, P, MODE, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, x, Qw, a.Bp,
+                                               active, wave, lane);
         if (x < ge)
-            group_steps_tail<NW, TW, P, 0, U>(acc, ring, lds, a.D, a.row_bytes, lane_off, x, ge - x, Qw, a.Bp,
-                                              active, wave, lane);
+            group_steps_tail<NW, TW, P, MODE, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, x, ge - x,
+                                                    Qw, a.Bp, active, wave, lane);
     }
 
     if (active && col_ok) {
@@ -224,52 +302,85 @@ void xorpir_m4rw_kernel(const WideArgs a)
 }
 
 // Qs[g * Bp + r] = (bits 6g .. 6g+5 of request row r, bits >= n cleared) *
-// ENTRY_BYTES; rows B <= r < Bp are zero. One thread per (group, row).
+// ENTRY_BYTES; rows B <= r < Bp and the extra group g = groups are zero. One
+// thread per (chunk of 32 groups, row): the chunk's 192 request bits are
+// exactly words 6c .. 6c+5 of the row, and a wave covers 64 consecutive rows,
+// so each group's 64 offsets go out as one contiguous store.
+constexpr int STAGE_CHUNK = 32;  // groups per thread (32 x 6 bits = 6 words)
+
 __global__ __launch_bounds__(256) void stage_wide_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
                                                                  uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
                                                                  uint32_t Bp, uint64_t groups)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= groups * Bp)
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t chunks = (groups + 1 + STAGE_CHUNK - 1) / STAGE_CHUNK;
+    const uint64_t c = t / Bp;
+    const uint32_t r = (uint32_t)(t % Bp);
+    if (c >= chunks)
         return;
-    const uint64_t g = i / Bp;
-    const uint32_t r = (uint32_t)(i % Bp);
-    uint32_t v = 0;
-    if (r < B) {
-        const uint64_t nwords = (n + 31) >> 5;
-        const uint64_t bit = g * GB;
-        const uint64_t w = bit >> 5;
-        const uint32_t sh = (uint32_t)(bit & 31u);
-        const uint32_t *row = Q + (uint64_t)r * qpitch_w;
-        uint64_t win = row[w];
-        if (w + 1 < nwords)
-            win |= (uint64_t)row[w + 1] << 32;
-        v = (uint32_t)(win >> sh) & (ENTRIES - 1);
-        if (bit + GB > n) {
-            const uint64_t keep = n > bit ? n - bit : 0;
-            v &= (1u << keep) - 1u;
-        }
+    const uint64_t nwords = (n + 31) >> 5;
+    uint32_t w[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const uint64_t wi = c * 6 + j;
+        w[j] = (j < 6 && r < B && wi < nwords) ? Q[(uint64_t)r * qpitch_w + wi] : 0u;
     }
-    Qs[i] = v * ENTRY_BYTES;
+    const uint64_t g0 = c * STAGE_CHUNK;
+#pragma unroll
+    for (int k = 0; k < STAGE_CHUNK; ++k) {
+        const uint64_t g = g0 + k;
+        if (g > groups)
+            break;
+        const int j = (6 * k) >> 5, sh = (6 * k) & 31;
+        const uint64_t win = (uint64_t)w[j] | ((uint64_t)w[j + 1] << 32);
+        uint32_t v = (uint32_t)(win >> sh) & (ENTRIES - 1);
+        const uint64_t bit = g * GB;
+        if (bit + GB > n)
+            v &= bit >= n ? 0u : (1u << (n - bit)) - 1u;
+        Qs[g * Bp + r] = v * ENTRY_BYTES;
+    }
 }
 
 using WideFn = void (*)(const WideArgs);
 
-// Prefetch depth comes from plan flags bits 8..11 (0 = 2 groups).
-WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth)
+// Prefetch depth comes from plan flags bits 8..11 (0 = the default: 2
+// groups, 1 with a single table), the lookup mode from bit 12 (PLAN_ROLLING)
+// and bit 13 (PLAN_SINGLE_TABLE: one 64 KiB table, rolling lookups, two
+// workgroups per CU).
+WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
 {
     if (depth == 0)
-        depth = 2;
-    if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2>;
-    if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<8, 16, 2>;
-    if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rw_kernel<8, 16, 4>;
-    if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2>;
-    if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rw_kernel<8, 32, 3>;
-    if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2>;
+        depth = mode == 2 ? 1 : 2;
+    if (mode == 0) {
+        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2, 0>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<8, 16, 2, 0>;
+        if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rw_kernel<8, 16, 4, 0>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2, 0>;
+        if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rw_kernel<8, 32, 3, 0>;
+        if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2, 0>;
+    } else if (mode == 1) {
+        if (nw == 4 && tw == 8 && depth == 2) return xorpir_m4rw_kernel<4, 8, 2, 1>;
+        if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<4, 16, 2, 1>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rw_kernel<8, 8, 2, 1>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<8, 16, 2, 1>;
+        if (nw == 8 && tw == 16 && depth == 3) return xorpir_m4rw_kernel<8, 16, 3, 1>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2, 1>;
+        if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2, 1>;
+    } else {
+        // a single table is built from data loaded `depth` steps earlier, so
+        // depth 1 hides as much load latency here as depth 2 does above
+        if (nw == 4 && tw == 32 && depth == 1) return xorpir_m4rw_kernel<4, 32, 1, 2>;
+        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2, 2>;
+        if (nw == 8 && tw == 16 && depth == 1) return xorpir_m4rw_kernel<8, 16, 1, 2>;
+    }
     return nullptr;
 }
 
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
+uint32_t plan_mode(const Plan &p)
+{
+    return (p.flags & PLAN_SINGLE_TABLE) ? 2u : (p.flags & PLAN_ROLLING) ? 1u : 0u;
+}
 
 uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
@@ -277,12 +388,15 @@ uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
 // Plan fields for this family: tile = requests per wave (TW), unroll = waves
 // per workgroup (NW).
-bool m4rw_plan_supported(const Plan &p) { return wide_fn(p.unroll, p.tile, plan_depth(p)) != nullptr; }
+bool m4rw_plan_supported(const Plan &p)
+{
+    return wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p)) != nullptr;
+}
 
 uint64_t m4rw_staging_bytes(const ReadGeom &g)
 {
     const uint64_t groups = (g.n + GB - 1) / GB;
-    return (groups * padded_rows(g.B) * 4 + 255) & ~255ull;
+    return ((groups + 1) * padded_rows(g.B) * 4 + 255) & ~255ull;
 }
 
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
@@ -298,7 +412,7 @@ uint64_t m4rw_groups(uint64_t n) { return (n + GB - 1) / GB; }
 hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
                      hipEvent_t ee)
 {
-    WideFn fn = wide_fn(p.unroll, p.tile, plan_depth(p));
+    WideFn fn = wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
     if (!fn)
         return hipErrorInvalidValue;
     WideArgs a{};
@@ -311,7 +425,7 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.groups = m4rw_groups(g.n);
     uint32_t *qs = static_cast<uint32_t *>(partials);
     {
-        const uint64_t threads = a.groups * a.Bp;
+        const uint64_t threads = (a.groups + 1 + STAGE_CHUNK - 1) / STAGE_CHUNK * a.Bp;
         hipLaunchKernelGGL(stage_wide_offsets_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, stream,
                            static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
         hipError_t e = hipGetLastError();

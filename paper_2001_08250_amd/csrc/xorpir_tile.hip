@@ -182,95 +182,6 @@ __global__ __launch_bounds__(WG) void xorpir_tile_kernel(const TileArgs a)
     }
 }
 
-// Persistent work-queue read over a stream of uneven batches. Workgroups
-// claim items with one atomic counter until the queue is empty (no waiting
-// on other workgroups, so every workgroup exits). Items are ordered batch by
-// batch. When a batch is split over bucket ranges, each split stores its
-// partial answer, publishes it (release fence + completion counter) and the
-// workgroup that completes a (batch, request tile, column group) last XORs
-// the partials into the response rows (acquire fence first).
-template <int KIND>
-__global__ __launch_bounds__(WG) void xorpir_queue_kernel(const QueueGeom g)
-{
-    constexpr int T = QUEUE_TILE;
-    constexpr int U = 8;
-    __shared__ uint32_t s_item;
-    __shared__ uint32_t s_last;
-    const uint32_t stride16 = (uint32_t)(g.stride / 16);
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t nwords = (g.n + 31) >> 5;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_item = atomicAdd(g.head, 1u);
-        __syncthreads();
-        const uint32_t it = s_item;
-        __syncthreads();
-        if (it >= g.n_items)
-            break;
-        const QueueItem item = g.items[it];
-        const QueueBatch bt = g.batches[item.batch];
-        const uint32_t wave_col = item.cg * COLS_PER_WG + wave * 64u;
-        const bool wave_ok = wave_col < stride16;
-        const uint32_t col = wave_col + lane;
-        const bool col_ok = wave_ok && col < stride16;
-        const uint32_t colc = col_ok ? col : (wave_ok ? wave_col : 0u);
-        const uint32_t r0 = item.rt * T;
-        const uint64_t wb = (uint64_t)item.s * bt.words_per_split;
-        const uint64_t we = std::min<uint64_t>(nwords, wb + bt.words_per_split);
-        const uint64_t jb = wb << 5;
-        const uint64_t je = std::min<uint64_t>(g.n, we << 5);
-        const uint32_t *Q = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g.Q) + bt.q_off);
-        uint4 acc[T];
-        if (wave_ok)
-            tile_accumulate<T, KIND, U>(acc, static_cast<const uint4 *>(g.D), stride16, g.n, Q, g.qpitch / 4,
-                                        bt.B, r0, colc, jb, je);
-        uint4 *out = reinterpret_cast<uint4 *>(static_cast<uint8_t *>(g.out) + bt.out_off);
-        const uint64_t out_row16 = g.out_pitch / 16;
-        if (bt.splits <= 1) {
-            if (col_ok) {
-#pragma unroll
-                for (int r = 0; r < T; ++r)
-                    if (r0 + r < bt.B)
-                        out[(uint64_t)(r0 + r) * out_row16 + col] = acc[r];
-            }
-            continue;
-        }
-        uint4 *part = reinterpret_cast<uint4 *>(static_cast<uint8_t *>(g.partials) + bt.part_off);
-        const uint64_t split16 = (uint64_t)bt.B * stride16;
-        if (col_ok) {
-#pragma unroll
-            for (int r = 0; r < T; ++r)
-                if (r0 + r < bt.B)
-                    part[(uint64_t)item.s * split16 + (uint64_t)(r0 + r) * stride16 + col] = acc[r];
-        }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t grp = bt.group_base + item.rt * bt.n_cg + item.cg;
-            s_last = (atomicAdd(g.done + grp, 1u) == bt.splits - 1) ? 1u : 0u;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if (col_ok) {
-                for (uint32_t r = r0; r < std::min<uint32_t>(r0 + T, bt.B); ++r) {
-                    uint4 x = make_uint4(0u, 0u, 0u, 0u);
-                    for (uint32_t s = 0; s < bt.splits; ++s) {
-                        const uint4 v = part[(uint64_t)s * split16 + (uint64_t)r * stride16 + col];
-                        x.x ^= v.x;
-                        x.y ^= v.y;
-                        x.z ^= v.z;
-                        x.w ^= v.w;
-                    }
-                    out[(uint64_t)r * out_row16 + col] = x;
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // resp[r][c] = XOR over s of partials[s][r][c]
 __global__ __launch_bounds__(WG) void xor_splits_kernel(const uint4 *__restrict__ P, uint64_t split16,
                                                         uint32_t splits, uint64_t count, uint32_t stride16,
@@ -280,6 +191,7 @@ __global__ __launch_bounds__(WG) void xor_splits_kernel(const uint4 *__restrict_
     if (i >= count)
         return;
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll 8
     for (uint32_t s = 0; s < splits; ++s) {
         const uint4 v = P[(uint64_t)s * split16 + i];
         acc.x ^= v.x;
@@ -330,14 +242,6 @@ TileFn tile_fn(const Plan &p)
 }
 
 }  // namespace
-
-uint32_t queue_grid(int num_cus) { return (uint32_t)std::max(num_cus, 1) * 4; }
-
-hipError_t launch_queue(const QueueGeom &g, uint32_t grid, hipStream_t stream)
-{
-    hipLaunchKernelGGL(xorpir_queue_kernel<KIND_SKIP>, dim3(grid), dim3(WG), 0, stream, g);
-    return hipGetLastError();
-}
 
 bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
 

@@ -48,7 +48,7 @@ C4B = Workload("xorpir-n1M-d2-z4k-B2048", n=1 << 20, d=2, z=4 * KiB, B=2048, db_
 C5 = Workload("serve-n1M-d4-z1k", n=1 << 20, d=4, z=1 * KiB, fill="cuckoo", cuckoo_items=3_145_728,
               cuckoo_seed=3005, req_seed=2005,
               extra={"arrival_seed": 4005, "rates": (5_000, 20_000, 50_000), "write_frac": 0.1,
-                     "interest_bits": 1 << 20, "interest_k": 6, "window": 8, "epoch_s": 1.0})
+                     "interest_bits": 1 << 17, "interest_k": 6, "window": 100, "epoch_s": 1.0})
 
 ALL = {w.name: w for w in (C1, C2, C3, C4A, C4B, C5)}
 BY_KEY = {"c1": C1, "c2": C2, "c3": C3, "c4a": C4A, "c4b": C4B, "c5": C5}

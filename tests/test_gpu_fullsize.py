@@ -49,12 +49,16 @@ def test_cuckoo_filled_65536_full_parity():
         say("oracle: 256 rows over 256 MiB")
         want = oracle.pir_read(D, req, threads=THREADS)
         assert_rows_equal(db.read(req), want, "auto plan")
-        for kind, tile, unroll in ((pir.KERNEL_MASK, 16, 8), (pir.KERNEL_SKIP, 16, 4), (pir.KERNEL_M4R, 16, 16),
-                                   (pir.KERNEL_M4R, 32, 8), (pir.KERNEL_M4R_WIDE, 32, 8),
-                                   (pir.KERNEL_M4R_WIDE, 16, 16)):
-            db.set_plan(kind, tile, 0, unroll)
-            say(f"kind={kind} tile={tile} unroll={unroll}")
-            assert_rows_equal(db.read(req), want, f"kind={kind}")
+        R = pir.PLAN_ROLLING
+        for kind, tile, unroll, fl in ((pir.KERNEL_MASK, 16, 8, 0), (pir.KERNEL_SKIP, 16, 4, 0),
+                                       (pir.KERNEL_M4R, 16, 16, 0), (pir.KERNEL_M4R, 32, 8, 0),
+                                       (pir.KERNEL_M4R_WIDE, 32, 8, 0), (pir.KERNEL_M4R_WIDE, 16, 16, 0),
+                                       (pir.KERNEL_M4R_WIDE, 16, 16, R), (pir.KERNEL_M4R_WIDE, 32, 8, R),
+                                       (pir.KERNEL_M4R_WIDE, 8, 4, R),
+                                       (pir.KERNEL_M4R_WIDE, 16, 8, pir.PLAN_SINGLE_TABLE)):
+            db.set_plan(kind, tile, 0, unroll, fl)
+            say(f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
+            assert_rows_equal(db.read(req), want, f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
 
 
 def _sampled(db, D, req, rows, what):
@@ -75,8 +79,9 @@ def test_large_batch_sampled_rows(key):
         db.load(D)
         say(f"{w.name}: auto plan {db.get_plan(w.B)}")
         _sampled(db, D, req, rows, f"{w.name} auto")
-        for kind, tile, unroll in ((pir.KERNEL_MASK, 16, 8), (pir.KERNEL_M4R, 32, 16), (pir.KERNEL_M4R_WIDE, 32, 8)):
-            db.set_plan(kind, tile, 0, unroll)
+        for kind, tile, unroll, fl in ((pir.KERNEL_MASK, 16, 8, 0), (pir.KERNEL_M4R, 32, 16, 0),
+                                       (pir.KERNEL_M4R_WIDE, 32, 8, 0), (pir.KERNEL_M4R_WIDE, 16, 16, pir.PLAN_ROLLING)):
+            db.set_plan(kind, tile, 0, unroll, fl)
             say(f"{w.name}: kind={kind} tile={tile}")
             _sampled(db, D, req, rows[:4], f"{w.name} kind={kind}")
 

@@ -55,7 +55,11 @@ def test_small_workload_every_tile_schedule(kind):
 
 
 M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
-WIDE_SHAPES = [(4, 32, 2), (8, 16, 2), (8, 16, 4), (8, 32, 2), (8, 32, 3), (16, 16, 2)]  # waves, tile, depth
+_R, _S = pir.PLAN_ROLLING, pir.PLAN_SINGLE_TABLE
+# (waves, requests per wave, flags = prefetch depth << 8 | lookup mode)
+WIDE_SHAPES = [(4, 32, 2 << 8), (8, 16, 2 << 8), (8, 16, 4 << 8), (8, 32, 2 << 8), (8, 32, 3 << 8), (16, 16, 2 << 8),
+               (4, 8, _R), (4, 16, _R), (8, 8, _R), (8, 16, _R), (8, 16, _R | 3 << 8), (8, 32, _R), (16, 16, _R),
+               (8, 16, _S), (4, 32, _S), (4, 32, _S | 2 << 8)]
 FOUR_RUSSIANS = ([(pir.KERNEL_M4R, (nw, tw, 0)) for nw, tw in M4R_SHAPES] +
                  [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES])
 
@@ -68,14 +72,14 @@ def test_four_russians_every_shape(kind):
     reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300)}
     wants = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
     with _db(D, d, z) as db:
-        for k, (nw, tw, depth) in FOUR_RUSSIANS:
+        for k, (nw, tw, fl) in FOUR_RUSSIANS:
             if k != kind:
                 continue
             for sp in (1, 0, 7):
-                db.set_plan(kind, tw, sp, nw, depth << 8)
+                db.set_plan(kind, tw, sp, nw, fl)
                 for B, r in reqs.items():
-                    say(f"kind={kind} nw={nw} tw={tw} depth={depth} splits={sp} B={B}")
-                    assert_rows_equal(db.read(r), wants[B], f"kind={kind} nw={nw} tw={tw} P={depth} S={sp} B={B}")
+                    say(f"kind={kind} nw={nw} tw={tw} flags={fl:#x} splits={sp} B={B}")
+                    assert_rows_equal(db.read(r), wants[B], f"kind={kind} nw={nw} tw={tw} fl={fl:#x} S={sp} B={B}")
 
 
 @pytest.mark.parametrize("n,d,z,B", [(37, 3, 20, 5), (1000, 1, 8, 70), (333, 2, 520, 17), (4097, 4, 1024, 133),
@@ -88,10 +92,10 @@ def test_four_russians_ragged_shapes(n, d, z, B):
         for nw, tw in ((4, 32), (8, 16), (16, 32)):
             db.set_plan(pir.KERNEL_M4R, tw, 0, nw)
             assert_rows_equal(db.read(req), want, f"m4r nw={nw} tw={tw}")
-        for nw, tw, depth in WIDE_SHAPES:
+        for nw, tw, fl in WIDE_SHAPES:
             for sp in (0, 3):
-                db.set_plan(pir.KERNEL_M4R_WIDE, tw, sp, nw, depth << 8)
-                assert_rows_equal(db.read(req), want, f"m4r-wide nw={nw} tw={tw} P={depth} S={sp}")
+                db.set_plan(pir.KERNEL_M4R_WIDE, tw, sp, nw, fl)
+                assert_rows_equal(db.read(req), want, f"m4r-wide nw={nw} tw={tw} fl={fl:#x} S={sp}")
 
 
 def test_four_russians_one_hot_and_densities():
@@ -201,6 +205,31 @@ def test_epoch_visibility_and_double_buffering():
         assert db.epoch == 4
 
 
+@pytest.mark.parametrize("m_bits,window", [(1000, 1), (4096, 3), (1 << 17, 100)])
+def test_interest_window_across_commits(m_bits, window):
+    """Global interest vector after each commit = OR of the last `window`
+    epochs' positions; epochs with no positions, with bucket writes (swap
+    path) and without (vector-only path); the default configuration too."""
+    n, d, z = 64, 2, 32
+    rng = np.random.default_rng(m_bits + window)
+    D = synth.uniform_db(93, n, d * z)
+    with _db(D, d, z) as db:
+        if (m_bits, window) != (pir.IV_DEFAULT_BITS, pir.IV_DEFAULT_WINDOW):
+            db.interest_config(m_bits, window)
+        epochs = [np.zeros(0, np.uint32)]          # commit 0 = the load
+        for e in range(1, 12):
+            k = 0 if e % 4 == 0 else int(rng.integers(1, 40))
+            pos = rng.integers(0, m_bits, size=k, dtype=np.uint32)
+            if k:
+                db.interest_add(pos)
+            if e % 3 == 1:
+                db.write_bucket(int(rng.integers(0, n)), synth.uniform_bytes(e, d * z))
+            db.commit()
+            epochs.append(pos)
+            want = oracle.interest_window(m_bits, epochs, len(epochs) - 1, window)
+            assert np.array_equal(db.interest_vector(), want), f"epoch {e}"
+
+
 def test_write_errors():
     with pir.PirDB(16, 2, 8) as db:
         with pytest.raises(pir.PirError) as e:
@@ -259,6 +288,57 @@ def test_stream_of_uneven_batches_matches_single_reads():
                 want = oracle.pir_read(D, pool[int(first[k]):int(first[k]) + s], threads=8)
                 assert_rows_equal(got[row:row + s], want, f"rep {rep} batch {k} (B={s})")
                 row += s
+
+
+def test_stream_fuses_batches_with_scattered_rows():
+    """Batches fused into 1024-row launch groups (some batches split across
+    two groups), request rows gathered from anywhere in the pool and responses
+    scattered to permuted rows, replayed from the graph; then the same stream
+    contiguous (no gather/scatter)."""
+    import torch
+    n, d, z = 2048, 4, 1024
+    D = synth.uniform_db(75, n, d * z)
+    sizes = synth.batch_sizes(76, 40, 1, 120)          # ~2400 rows: batches straddle 1024-row groups
+    sizes[[0, 7, 39]] = 0
+    total = int(sizes.sum())
+    pool = synth.bernoulli_requests(77, 300, n)
+    rng = np.random.default_rng(78)
+    first = np.array([rng.integers(0, 300 - s + 1) for s in sizes], dtype=np.uint64)
+    # response blocks in a permuted order with gaps between them
+    order = rng.permutation(len(sizes))
+    resp_first = np.zeros(len(sizes), dtype=np.uint64)
+    row = 5
+    for k in order:
+        resp_first[k] = row
+        row += int(sizes[k]) + 3
+    dev = torch.device("cuda:0")
+    want_rows = {}
+    with _db(D, d, z) as db:
+        q = torch.from_numpy(pool).to(dev)
+        out = torch.zeros((row + 4, d * z), dtype=torch.uint8, device=dev)
+        for rep in range(2):
+            out.zero_()
+            db.read_stream_async(q, sizes, out, req_first=first, resp_first=resp_first)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            touched = np.zeros(row + 4, dtype=bool)
+            for k, s in enumerate(sizes):
+                s = int(s)
+                if s == 0:
+                    continue
+                if k not in want_rows:
+                    want_rows[k] = oracle.pir_read(D, pool[int(first[k]):int(first[k]) + s], threads=8)
+                r0 = int(resp_first[k])
+                assert_rows_equal(got[r0:r0 + s], want_rows[k], f"rep {rep} batch {k} (B={s})")
+                touched[r0:r0 + s] = True
+            assert not got[~touched].any(), "rows outside the response blocks were written"
+        # contiguous layout: no gather, no scatter
+        out2 = torch.zeros((total, d * z), dtype=torch.uint8, device=dev)
+        cat = np.concatenate([pool[int(first[k]):int(first[k]) + int(s)] for k, s in enumerate(sizes)])
+        q2 = torch.from_numpy(cat).to(dev)
+        db.read_stream_async(q2, sizes, out2)
+        torch.cuda.synchronize()
+        assert_rows_equal(out2.cpu().numpy(), oracle.pir_read(D, cat, threads=8), "contiguous stream")
 
 
 def test_tuner_picks_a_correct_plan(tmp_path):
