@@ -168,10 +168,8 @@ enum pir_kernel_kind {
  * workgroup instead of once per wave. Bits 8..11 (M4R_WIDE): how many
  * bucket groups ahead D is loaded (0 = 2). ROLLING (M4R_WIDE): table
  * lookups keep a fixed number of LDS reads in flight and the next group's
- * request offsets are fetched during the current one. SINGLE_TABLE
- * (M4R_WIDE, implies rolling lookups): one table buffer per workgroup
- * instead of two, so two workgroups share a CU. */
-enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12, PIR_PLAN_SINGLE_TABLE = 1 << 13 };
+ * request offsets are fetched during the current one. */
+enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12 };
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
  * splits (0 = heuristic), unroll (MASK/SKIP: buckets loaded ahead; M4R:

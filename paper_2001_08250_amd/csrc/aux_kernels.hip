@@ -5,9 +5,10 @@
 // staged buckets are scattered into the back copy of the database, and after
 // the swap the same buckets are copied into the new back copy.
 //
-// Interest vector (section "Private Notifications"): each write ORs its
-// interest-vector bits into the open epoch's delta; the published global
-// vector is the OR of the last `window` deltas.
+// Interest vector (section "Private Notifications"): the writes of an epoch
+// OR their interest-vector bits into that epoch's delta; the published global
+// vector is the OR of the last `window` deltas. Both are built by the commit
+// kernel, in the same launch that applies the staged bucket rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,46 +40,54 @@ __global__ __launch_bounds__(WG) void fill_zero_kernel(uint32_t *__restrict__ p,
 }
 
 // bit p lives in word p >> 5, bit p & 31 (little-endian: byte p >> 3, bit p & 7)
-__global__ __launch_bounds__(WG) void set_bits_kernel(uint32_t *__restrict__ words, const uint32_t *__restrict__ pos,
-                                                      uint64_t count)
+// The device half of an epoch commit, one launch. Blocks below iv_blocks
+// each own 64 words of the interest vector: they OR the window's other
+// slots, build the new epoch's delta from the positions that fall into their
+// words (the host sorted them by block), store the delta in its ring slot
+// (overwriting the epoch that leaves the window) and write the new global
+// vector. The remaining blocks copy one staged bucket row each (read in
+// place from mapped host memory) into the back copy.
+__global__ __launch_bounds__(WG) void commit_kernel(const CommitArgs a)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= count)
+    const uint64_t b = blockIdx.x;
+    if (b >= a.iv_blocks) {
+        const uint64_t e = b - a.iv_blocks;
+        const uint64_t row = a.idx[e];
+        const uint4 *s = a.rows + e * a.stride16;
+        uint4 *d = a.back + row * a.stride16;
+        for (uint64_t c = threadIdx.x; c < a.stride16; c += WG)
+            d[c] = s[c];
         return;
-    const uint32_t p = pos[i];
-    atomicOr(words + (p >> 5), 1u << (p & 31u));
-}
-
-// out[i] = OR over r < nrows of rows[r * words + i], then row clear_row is
-// zeroed. A workgroup takes 64 consecutive words; its four waves OR
-// interleaved quarters of the rows (64 consecutive words per load, several
-// loads in flight) and combine them through LDS. Each (row, word) is read by
-// one thread only, which also clears it when it belongs to clear_row.
-__global__ __launch_bounds__(WG) void or_rows_kernel(uint32_t *__restrict__ out, uint32_t *__restrict__ rows,
-                                                     uint32_t nrows, uint64_t words, uint32_t clear_row)
-{
+    }
     __shared__ uint32_t part[WG / 64][64];
+    __shared__ uint32_t fresh[64];
     const uint32_t lane = threadIdx.x & 63u, sl = threadIdx.x >> 6;
-    for (uint64_t base = (uint64_t)blockIdx.x * 64; base < words; base += (uint64_t)gridDim.x * 64) {
-        const uint64_t i = base + lane;
-        uint32_t v = 0;
-        if (i < words) {
+    const uint64_t i = b * 64 + lane;
+    if (threadIdx.x < 64)
+        fresh[threadIdx.x] = 0u;
+    uint32_t v = 0;
+    if (i < a.words) {
 #pragma unroll 4
-            for (uint32_t r = sl; r < nrows; r += WG / 64)
-                v |= rows[(uint64_t)r * words + i];
-            if (clear_row < nrows && clear_row % (WG / 64) == sl)
-                rows[(uint64_t)clear_row * words + i] = 0u;
-        }
-        part[sl][lane] = v;
-        __syncthreads();
-        if (sl == 0 && i < words) {
-            uint32_t o = 0;
+        for (uint32_t r = sl; r < a.window; r += WG / 64)
+            if (r != a.slot)
+                v |= a.ring[(uint64_t)r * a.words + i];
+    }
+    part[sl][lane] = v;
+    __syncthreads();
+    for (uint32_t j = a.pos_start[b] + threadIdx.x; j < a.pos_start[b + 1]; j += WG) {
+        const uint32_t p = a.pos[j];
+        const uint64_t w = (uint64_t)(p >> 5) - b * 64;
+        if (w < 64)
+            atomicOr(&fresh[w], 1u << (p & 31u));
+    }
+    __syncthreads();
+    if (sl == 0 && i < a.words) {
+        uint32_t o = fresh[lane];
+        a.ring[(uint64_t)a.slot * a.words + i] = o;
 #pragma unroll
-            for (int k = 0; k < WG / 64; ++k)
-                o |= part[k][lane];
-            out[i] = o;
-        }
-        __syncthreads();
+        for (int k = 0; k < WG / 64; ++k)
+            o |= part[k][lane];
+        a.global[i] = o;
     }
 }
 
@@ -267,23 +276,14 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count, hipStream_t stream)
+hipError_t launch_commit(const CommitArgs &a, hipStream_t stream)
 {
-    if (count == 0)
+    const uint64_t blocks = a.iv_blocks + a.nrows;
+    if (blocks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(set_bits_kernel, dim3((uint32_t)((count + WG - 1) / WG)), dim3(WG), 0, stream, words, pos,
-                       count);
-    return hipGetLastError();
-}
-
-hipError_t launch_or_rows(uint32_t *out, uint32_t *rows, uint32_t nrows, uint64_t words, uint32_t clear_row,
-                          hipStream_t stream)
-{
-    if (words == 0)
-        return hipSuccess;
-    const uint64_t chunks = (words + 63) / 64;
-    hipLaunchKernelGGL(or_rows_kernel, dim3((uint32_t)std::min<uint64_t>(chunks, 65536)), dim3(WG), 0, stream, out,
-                       rows, nrows, words, clear_row);
+    if (blocks > 0x7fffffffull)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(commit_kernel, dim3((uint32_t)blocks), dim3(WG), 0, stream, a);
     return hipGetLastError();
 }
 

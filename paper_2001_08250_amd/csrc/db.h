@@ -88,7 +88,8 @@ struct pir_db {
     std::vector<uint32_t> pos_pending;
     uint32_t *pos_host = nullptr;      // mapped pinned
     void *pos_map = nullptr;
-    uint64_t pos_host_cap = 0;
+    uint64_t pos_host_cap = 0;         // u32 entries
+    std::vector<uint32_t> pos_cursor;  // counting-sort cursors
 
     // Each mapped pinned buffer is free for the host again once its event
     // (recorded after the kernel that reads it) has completed: 0 = staged

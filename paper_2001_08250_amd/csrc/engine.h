@@ -42,7 +42,6 @@ struct Plan {
 };
 constexpr uint32_t PLAN_SHARED_COLUMN = 1;
 constexpr uint32_t PLAN_ROLLING = 1u << 12;
-constexpr uint32_t PLAN_SINGLE_TABLE = 1u << 13;
 
 // Device scratch the read needs for split partials: bytes.
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p);
@@ -93,11 +92,22 @@ hipError_t launch_gather_rows(void *dst, uint64_t dst_pitch, const void *src, ui
 
 // --- interest vector -----------------------------------------------------
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);           // bytes % 4 == 0
-hipError_t launch_set_bits(uint32_t *words, const uint32_t *pos, uint64_t count, hipStream_t stream);
-// out = OR of the nrows rows of `words` words; row clear_row (< nrows, or
-// none) is zeroed after it has been read.
-hipError_t launch_or_rows(uint32_t *out, uint32_t *rows, uint32_t nrows, uint64_t words, uint32_t clear_row,
-                          hipStream_t stream);
+// Epoch commit, device half (one launch): staged rows into the back copy and
+// the interest-vector update (see commit_kernel).
+struct CommitArgs {
+    uint4 *back;               // back copy
+    const uint4 *rows;         // nrows staged rows (stride16 uint4 each), mapped host memory
+    const uint64_t *idx;       // their bucket indices, mapped host memory
+    uint64_t nrows, stride16;
+    uint32_t *global;          // global vector to write (the back copy's)
+    uint32_t *ring;            // window x words deltas
+    uint32_t window, slot;     // slot = this epoch's delta
+    uint64_t words, iv_blocks; // iv_blocks = ceil(words / 64)
+    const uint32_t *pos;       // positions sorted by 64-word block, mapped host memory
+    const uint32_t *pos_start; // block b: pos[pos_start[b] .. pos_start[b + 1])
+};
+hipError_t launch_commit(const CommitArgs &a, hipStream_t stream);
+
 
 
 }  // namespace talek

@@ -441,44 +441,69 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
         return PIR_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     HIP_TRY(hipSetDevice(db->device));
-    PIR_TRY(flush_stage(db));
+    const uint64_t rows = db->stage_rows;
+    for (uint64_t i = 0; i < rows; ++i)
+        mark_dirty(db, db->stage_idx_host[i]);
     const bool changed = db->all_dirty || !db->dirty.empty();
     const int back = db->front ^ 1;
+    if (changed)
+        PIR_TRY(ensure_back(db));
 
-    // interest vector: the open epoch's delta replaces the oldest ring slot;
-    // the new global vector (OR of the window) goes with the back copy.
-    // The ring slot of this epoch is all zero (cleared by the previous
-    // commit's OR, or at configuration); the positions are read in place
-    // from mapped host memory.
+    // Interest vector: the open epoch's delta replaces the ring slot of the
+    // epoch that leaves the window, and the new global vector (OR of the
+    // window) goes with the back copy. The positions go to the kernel sorted
+    // by 64-word block (counting sort), in mapped host memory.
     PIR_TRY(wait_upload(db, UP_POS));
     const uint64_t npos = db->pos_pending.size();
-    if (npos > db->pos_host_cap) {
+    const uint64_t nb = (db->iv_words + 63) / 64;
+    if (npos + nb + 1 > db->pos_host_cap) {
         if (db->pos_host)
             hipHostFree(db->pos_host);
         db->pos_host = nullptr;
         db->pos_host_cap = 0;
         void *p = nullptr;
-        PIR_TRY(host_mapped(npos * 4, &p, &db->pos_map));
+        PIR_TRY(host_mapped((npos + nb + 1) * 4, &p, &db->pos_map));
         db->pos_host = static_cast<uint32_t *>(p);
-        db->pos_host_cap = npos;
+        db->pos_host_cap = npos + nb + 1;
     }
-    uint32_t *slot = db->iv_ring + (db->epoch % db->window) * db->iv_words;
-    if (npos) {
-        memcpy(db->pos_host, db->pos_pending.data(), npos * 4);
-        HIP_TRY(launch_set_bits(slot, static_cast<const uint32_t *>(db->pos_map), npos, db->stream));
-        PIR_TRY(note_upload(db, UP_POS));
-    }
+    uint32_t *start = db->pos_host, *sorted = db->pos_host + nb + 1;
+    memset(start, 0, (nb + 1) * 4);
+    for (uint32_t p : db->pos_pending)
+        ++start[(p >> 5) / 64 + 1];
+    for (uint64_t b = 0; b < nb; ++b)
+        start[b + 1] += start[b];
+    db->pos_cursor.assign(start, start + nb);
+    for (uint32_t p : db->pos_pending)
+        sorted[db->pos_cursor[(p >> 5) / 64]++] = p;
+
     // The back copy's vector may still be read by async readers of the
-    // buffer it belonged to before the last swap. The OR also clears the
-    // slot of the oldest epoch of this window, which the next commit fills.
+    // buffer it belonged to before the last swap.
     PIR_TRY(wait_readers(db, back, db->stream));
-    HIP_TRY(launch_or_rows(db->iv_global[back], db->iv_ring, db->window, db->iv_words,
-                           (uint32_t)((db->epoch + 1) % db->window), db->stream));
+    CommitArgs ca{};
+    ca.back = reinterpret_cast<uint4 *>(db->buf[back]);
+    ca.rows = static_cast<const uint4 *>(db->stage_map);
+    ca.idx = static_cast<const uint64_t *>(db->stage_idx_map);
+    ca.nrows = rows;
+    ca.stride16 = db->stride / 16;
+    ca.global = db->iv_global[back];
+    ca.ring = db->iv_ring;
+    ca.window = db->window;
+    ca.slot = (uint32_t)(db->epoch % db->window);
+    ca.words = db->iv_words;
+    ca.iv_blocks = nb;
+    const uint32_t *pos_dev = static_cast<const uint32_t *>(db->pos_map);
+    ca.pos_start = pos_dev;
+    ca.pos = pos_dev + nb + 1;
+    HIP_TRY(launch_commit(ca, db->stream));
+    PIR_TRY(note_upload(db, UP_POS));
+    if (rows) {
+        PIR_TRY(note_upload(db, UP_STAGE));  // the staging rows are refilled only after this
+        db->stage_rows = 0;
+        db->stage_slot.clear();
+    }
     db->pos_pending.clear();
 
-    if (changed) {
-        PIR_TRY(ensure_back(db));
-    } else if (!db->have_back) {
+    if (!changed && !db->have_back) {
         // nothing written: only the interest vector moves. Keep the
         // snapshot where it is and copy the new vector into the front slot.
         PIR_TRY(wait_readers(db, db->front, db->stream));

@@ -88,9 +88,7 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         if (p.unroll == 0)
             p.unroll = 8;
         units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
-        // two 64 KiB tables fill a CU's LDS; a single table leaves room for a
-        // second workgroup
-        per_cu = (p.flags & PLAN_SINGLE_TABLE) ? 2 : 1;
+        per_cu = 1;  // the two 64 KiB tables fill a CU's LDS
     } else {
         if (p.tile == 0)
             p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;

@@ -148,10 +148,7 @@ __device__ __forceinline__ void lookup_rolling(uint4 (&acc)[TW], const uint8_t *
 // looked up in batches. MODE 1: offs already holds them (loaded at the end of
 // the previous step, so they landed in the wait that precedes the barrier);
 // lookups are rolling, and the next group's offsets are loaded after them
-// (the staging area has one zero group past the end). MODE 2: as MODE 1 with
-// a single table buffer: build, barrier, look up, barrier. Half the LDS, so
-// two workgroups share a CU and overlap one's table build with the other's
-// lookups.
+// (the staging area has one zero group past the end).
 template <int NW, int TW, int P, int MODE, int K>
 __device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[P][GB], uint32_t (&offs)[TW],
                                            uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
@@ -160,26 +157,16 @@ __device__ __forceinline__ void group_step(uint4 (&acc)[TW], uint4 (&ring)[P][GB
 {
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
     const uint32_t *q = Qw + x * Bp;
-    const uint8_t *tbl;
-    if constexpr (MODE == 2) {
-        // one table buffer: build group x (loaded P steps ago), refill its
-        // ring slot with group x + P, and let every wave finish the table
-        build_table<NW>(lds, ring[slot], wave, lane);
-        load_group(ring[slot], D, row_bytes, lane_off, x + P);
-        __syncthreads();
-        tbl = reinterpret_cast<const uint8_t *>(lds + lane);
-    } else {
-        load_group(ring[slot], D, row_bytes, lane_off, x + P);
-        build_table<NW>(lds + (buf ^ 1) * TABLE_U4, ring[next], wave, lane);
-        tbl = reinterpret_cast<const uint8_t *>(lds + buf * TABLE_U4 + lane);
-    }
+    load_group(ring[slot], D, row_bytes, lane_off, x + P);
+    build_table<NW>(lds + (buf ^ 1) * TABLE_U4, ring[next], wave, lane);
+    const uint8_t *tbl = reinterpret_cast<const uint8_t *>(lds + buf * TABLE_U4 + lane);
     if (active) {
-        if constexpr (MODE >= 1)
-            lookup_rolling<TW, (NW >= 16 || MODE == 2 ? 4 : 8)>(acc, tbl, offs);
+        if constexpr (MODE == 1)
+            lookup_rolling<TW, (NW >= 16 ? 4 : 8)>(acc, tbl, offs);
         else
             lookup<TW, (NW >= 16 ? 4 : 8)>(acc, tbl, q);
     }
-    if (MODE >= 1 && active) {
+    if (MODE == 1 && active) {
         // Rows r0 .. r0 + TW - 1 < Bp (r0 < B, TW divides 64) of group
         // x + 1 <= groups: inside the staging area. The group index goes
         // through readfirstlane so loop strength reduction cannot split the
@@ -227,21 +214,13 @@ __device__ __forceinline__ void group_steps_tail(uint4 (&acc)[TW], uint4 (&ring)
     }
 }
 
-// Waves per SIMD to reserve registers for: one workgroup per CU, two in
-// MODE 2.
-template <int NW, int MODE>
-constexpr int waves_per_simd()
-{
-    return (MODE == 2 ? 2 : 1) * NW / 4;
-}
-
+// One workgroup per CU (its two tables fill the LDS): NW / 4 waves per SIMD.
 template <int NW, int TW, int P, int MODE>
-__global__ __launch_bounds__(NW * 64)
-__attribute__((amdgpu_waves_per_eu(waves_per_simd<NW, MODE>(), waves_per_simd<NW, MODE>())))
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void xorpir_m4rw_kernel(const WideArgs a)
 {
     constexpr int U = (P % 2 == 0) ? P : 2 * P;  // lcm(P, 2)
-    __shared__ uint4 lds[(MODE == 2 ? 1 : 2) * TABLE_U4];
+    __shared__ uint4 lds[2 * TABLE_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
     if (t >= a.n_rt * a.slices * a.splits)
@@ -274,15 +253,13 @@ void xorpir_m4rw_kernel(const WideArgs a)
             load_group(ring[k], a.D, a.row_bytes, lane_off, gb + k);
         const uint32_t *Qw = a.Qs + r0;
         uint32_t offs[TW] = {};
-        if (MODE >= 1 && active) {
+        if (MODE == 1 && active) {
 #pragma unroll
             for (int i = 0; i < TW; ++i)
                 offs[i] = Qw[gb * a.Bp + i];
         }
-        if constexpr (MODE != 2) {
-            build_table<NW>(lds, ring[0], wave, lane);
-            __syncthreads();
-        }
+        build_table<NW>(lds, ring[0], wave, lane);
+        __syncthreads();
         uint64_t x = gb;
         for (; x + U <= ge; x += U)
             group_steps<NW, TW, P, MODE, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, x, Qw, a.Bp,
@@ -343,14 +320,12 @@ __global__ __launch_bounds__(256) void stage_wide_offsets_kernel(const uint32_t 
 
 using WideFn = void (*)(const WideArgs);
 
-// Prefetch depth comes from plan flags bits 8..11 (0 = the default: 2
-// groups, 1 with a single table), the lookup mode from bit 12 (PLAN_ROLLING)
-// and bit 13 (PLAN_SINGLE_TABLE: one 64 KiB table, rolling lookups, two
-// workgroups per CU).
+// Prefetch depth comes from plan flags bits 8..11 (0 = 2 groups), the
+// lookup mode from bit 12 (PLAN_ROLLING).
 WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
 {
     if (depth == 0)
-        depth = mode == 2 ? 1 : 2;
+        depth = 2;
     if (mode == 0) {
         if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2, 0>;
         if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<8, 16, 2, 0>;
@@ -358,7 +333,7 @@ WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
         if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2, 0>;
         if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rw_kernel<8, 32, 3, 0>;
         if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2, 0>;
-    } else if (mode == 1) {
+    } else {
         if (nw == 4 && tw == 8 && depth == 2) return xorpir_m4rw_kernel<4, 8, 2, 1>;
         if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<4, 16, 2, 1>;
         if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rw_kernel<8, 8, 2, 1>;
@@ -366,21 +341,12 @@ WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
         if (nw == 8 && tw == 16 && depth == 3) return xorpir_m4rw_kernel<8, 16, 3, 1>;
         if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<8, 32, 2, 1>;
         if (nw == 16 && tw == 16 && depth == 2) return xorpir_m4rw_kernel<16, 16, 2, 1>;
-    } else {
-        // a single table is built from data loaded `depth` steps earlier, so
-        // depth 1 hides as much load latency here as depth 2 does above
-        if (nw == 4 && tw == 32 && depth == 1) return xorpir_m4rw_kernel<4, 32, 1, 2>;
-        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rw_kernel<4, 32, 2, 2>;
-        if (nw == 8 && tw == 16 && depth == 1) return xorpir_m4rw_kernel<8, 16, 1, 2>;
     }
     return nullptr;
 }
 
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
-uint32_t plan_mode(const Plan &p)
-{
-    return (p.flags & PLAN_SINGLE_TABLE) ? 2u : (p.flags & PLAN_ROLLING) ? 1u : 0u;
-}
+uint32_t plan_mode(const Plan &p) { return (p.flags & PLAN_ROLLING) ? 1u : 0u; }
 
 uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 

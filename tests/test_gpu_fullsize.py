@@ -54,8 +54,7 @@ def test_cuckoo_filled_65536_full_parity():
                                        (pir.KERNEL_M4R, 16, 16, 0), (pir.KERNEL_M4R, 32, 8, 0),
                                        (pir.KERNEL_M4R_WIDE, 32, 8, 0), (pir.KERNEL_M4R_WIDE, 16, 16, 0),
                                        (pir.KERNEL_M4R_WIDE, 16, 16, R), (pir.KERNEL_M4R_WIDE, 32, 8, R),
-                                       (pir.KERNEL_M4R_WIDE, 8, 4, R),
-                                       (pir.KERNEL_M4R_WIDE, 16, 8, pir.PLAN_SINGLE_TABLE)):
+                                       (pir.KERNEL_M4R_WIDE, 8, 4, R)):
             db.set_plan(kind, tile, 0, unroll, fl)
             say(f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
             assert_rows_equal(db.read(req), want, f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
