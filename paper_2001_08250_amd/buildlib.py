@@ -11,6 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtalek_pir.so")
+PROBE = os.path.join(HERE, "lds_probe")  # LDS bandwidth probe (roofline figures of the table kernels)
 ARCH = os.environ.get("TALEK_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = [
@@ -58,6 +59,11 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    cmd = ["hipcc", "-O3", "-std=c++17", "-Wall", *DEVICE, os.path.join(CSRC, "lds_probe.hip"), "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 
