@@ -67,6 +67,14 @@ def measured_traffic(workload: str, plan) -> float | None:
 
 KERNEL_NAMES = {1: "xorpir_tile_kernel", 2: "xorpir_tile_kernel", 3: "xorpir_m4r_kernel",
                 4: "xorpir_m4rw_kernel"}
+PLAN_PAIRS = 1 << 13
+
+
+def kernel_name(plan: dict) -> str:
+    """Name of the main read kernel a plan launches."""
+    if plan["kind"] == 4 and plan["flags"] & PLAN_PAIRS:
+        return "xorpir_m4rp_kernel"
+    return KERNEL_NAMES[plan["kind"]]
 
 
 def _counter_rows(d: str, counter: str):
@@ -96,7 +104,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str, calib_mib: 
     the same counter reads for a plain device copy of calib_mib MiB in the same run."""
     line = json.loads([x for x in open(bench_json) if x.startswith("{")][-1])
     plan = line["config"]["plan"]
-    name = KERNEL_NAMES[plan["kind"]]
+    name = kernel_name(plan)
     out = {"workload": line["config"]["workload"], "plan": plan,
            "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name,
            "calibration_copy_kib": calib_mib * 1024, "command": command}

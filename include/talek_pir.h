@@ -168,8 +168,11 @@ enum pir_kernel_kind {
  * workgroup instead of once per wave. Bits 8..11 (M4R_WIDE): how many
  * bucket groups ahead D is loaded (0 = 2). ROLLING (M4R_WIDE): table
  * lookups keep a fixed number of LDS reads in flight and the next group's
- * request offsets are fetched during the current one. */
-enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12 };
+ * request offsets are fetched during the current one. PAIRS (M4R_WIDE): two
+ * 5-bucket tables of 32 entries per step instead of one 6-bucket table,
+ * each request folding both lookups in with one 3-input XOR per dword
+ * (rolling lookups always). */
+enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12, PIR_PLAN_PAIRS = 1 << 13 };
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
  * splits (0 = heuristic), unroll (MASK/SKIP: buckets loaded ahead; M4R:

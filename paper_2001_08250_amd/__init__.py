@@ -26,6 +26,7 @@ PIR_OK, PIR_EINVAL, PIR_ERANGE, PIR_ENOMEM, PIR_EDEVICE, PIR_EFULL, PIR_EBUSY = 
 KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R, KERNEL_M4R_WIDE = 0, 1, 2, 3, 4
 PLAN_SHARED_COLUMN = 1
 PLAN_ROLLING = 1 << 12
+PLAN_PAIRS = 1 << 13
 PROFILE_MAX = 4096
 IV_DEFAULT_BITS, IV_DEFAULT_WINDOW = 1 << 17, 100   # the library's interest-vector defaults
 

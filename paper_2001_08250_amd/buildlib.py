@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtalek_pir.so")
-PROBE = os.path.join(HERE, "lds_probe")  # LDS bandwidth probe (roofline figures of the table kernels)
+PROBE = os.path.join(HERE, "roofline_probe")  # measured HBM, VALU and LDS peaks
 ARCH = os.environ.get("TALEK_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = [
@@ -59,7 +59,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    cmd = ["hipcc", "-O3", "-std=c++17", "-Wall", *DEVICE, os.path.join(CSRC, "lds_probe.hip"), "-o", PROBE + ".tmp"]
+    cmd = ["hipcc", "-O3", "-std=c++17", "-Wall", *DEVICE, os.path.join(CSRC, "roofline_probe.hip"), "-o", PROBE + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

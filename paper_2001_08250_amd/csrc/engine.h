@@ -42,6 +42,7 @@ struct Plan {
 };
 constexpr uint32_t PLAN_SHARED_COLUMN = 1;
 constexpr uint32_t PLAN_ROLLING = 1u << 12;
+constexpr uint32_t PLAN_PAIRS = 1u << 13;
 
 // Device scratch the read needs for split partials: bytes.
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p);

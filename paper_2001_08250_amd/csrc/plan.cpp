@@ -17,8 +17,8 @@ bool m4rw_plan_supported(const Plan &p);
 hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
                             hipEvent_t ee);
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p);
-uint64_t m4rw_staging_bytes(const ReadGeom &g);
-uint64_t m4rw_groups(uint64_t n);
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p);
+uint64_t m4rw_steps(uint64_t n, const Plan &p);
 
 namespace {
 
@@ -49,7 +49,7 @@ uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
     if (p.kind == KIND_M4R)
         bytes += m4r_staging_bytes(g);
     if (p.kind == KIND_M4RW)
-        bytes += m4rw_staging_bytes(g);
+        bytes += m4rw_staging_bytes(g, p);
     return bytes;
 }
 
@@ -57,15 +57,15 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
     if (p.kind == KIND_AUTO) {
-        // Small batches stream D with the plain tile kernels; from about
-        // 160 requests on, 64 KiB Four-Russians tables shared by 256
-        // requests per workgroup cost less than per-request XORs (below
-        // that the table builds dominate).
-        if (g.B >= 160) {
+        // Small batches stream D with the plain tile kernels; larger ones
+        // share paired 5-bucket Four-Russians tables among up to 256
+        // requests per workgroup (below about 64 requests the table builds
+        // cost more than they save).
+        if (g.B >= 64) {
             p.kind = KIND_M4RW;
-            p.flags = PLAN_ROLLING;
+            p.flags = PLAN_PAIRS;
             p.unroll = 8;
-            p.tile = 32;
+            p.tile = g.B >= 192 ? 32 : g.B >= 96 ? 16 : 8;
         } else {
             p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
         }
@@ -109,7 +109,7 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
             s = std::min<uint64_t>(s, std::max<uint64_t>(PARTIAL_CAP / per_split, 1));
         p.splits = (uint32_t)std::max<uint64_t>(s, 1);
     }
-    const uint64_t max_splits = p.kind == KIND_M4RW ? m4rw_groups(g.n) : nwords;
+    const uint64_t max_splits = p.kind == KIND_M4RW ? m4rw_steps(g.n, p) : nwords;
     p.splits = (uint32_t)std::min<uint64_t>(p.splits, std::max<uint64_t>(max_splits, 1));
     return p;
 }

@@ -1,11 +1,15 @@
-// LDS bandwidth probe for gfx950: aggregate LDS throughput of the access
-// patterns the Four-Russians kernels use. Every lane of a wave touches
-// consecutive bytes of one contiguous row slice (64 lanes x W dwords), so the
-// accesses are free of bank conflicts; all indices stay inside the 64 KiB
-// array. Reported per CU and clock at 2.4 GHz; these figures set the LDS
-// roofline of the table kernels.
+// Roofline probe for gfx950: the measured counterparts of the peaks the read
+// kernels are judged against.
+//   * HBM: a streaming read of a 4 GiB buffer (16 B per lane, coalesced).
+//   * VALU: 32-bit three-input bitwise operations (v_bitop3_b32), eight
+//     independent chains per lane.
+//   * LDS: aggregate throughput of the access patterns the Four-Russians
+//     kernels use. Every lane of a wave touches consecutive bytes of one
+//     contiguous row slice (64 lanes x W dwords), so the accesses are free of
+//     bank conflicts; all indices stay inside the 64 KiB array. Reported per
+//     CU and clock at 2.4 GHz.
 //
-//   ./paper_2001_08250_amd/lds_probe
+//   ./paper_2001_08250_amd/roofline_probe
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -66,6 +70,41 @@ __global__ __launch_bounds__(256) void lds_probe(uint32_t *out, int iters)
     out[blockIdx.x * 256 + threadIdx.x] = s[threadIdx.x] ^ acc.x ^ acc.y ^ acc.z ^ acc.w;
 }
 
+// Streaming read: every element of src once, XOR-folded per thread.
+__global__ __launch_bounds__(256) void hbm_read(const uint4 *__restrict__ src, uint64_t n16, uint32_t *out)
+{
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+#pragma unroll 4
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+        const uint4 v = src[i];
+        acc.x ^= v.x;
+        acc.y ^= v.y;
+        acc.z ^= v.z;
+        acc.w ^= v.w;
+    }
+    out[blockIdx.x * 256 + threadIdx.x] = acc.x ^ acc.y ^ acc.z ^ acc.w;
+}
+
+// Eight dependent chains of three-input XORs per lane (each op counts once).
+__global__ __launch_bounds__(256) void valu_bitop3(uint32_t *out, int iters)
+{
+    uint32_t a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        a[k] = threadIdx.x * (k + 3) + blockIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            a[k] = __builtin_amdgcn_bitop3_b32(a[k], a[(k + 1) & 7], a[(k + 3) & 7], 0x96);
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        r ^= a[k];
+    out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
 template <int MODE, int W>
 int run(const char *what, uint32_t *d, int cus)
 {
@@ -101,7 +140,47 @@ int main()
     uint32_t *d = nullptr;
     if (hipMalloc(&d, (size_t)p.multiProcessorCount * 8 * 256 * 4) != hipSuccess)
         return 1;
-    int rc = run<0, 1>("ds_read_b32 (4 B per lane)", d, p.multiProcessorCount);
+    const int cus = p.multiProcessorCount;
+    int rc = 0;
+    {   // HBM
+        const uint64_t bytes = 4ull << 30;
+        void *src = nullptr;
+        if (hipMalloc(&src, bytes) != hipSuccess || hipMemset(src, 1, bytes) != hipSuccess)
+            return 1;
+        const int grid = cus * 8;
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        hipLaunchKernelGGL(hbm_read, dim3(grid), dim3(256), 0, 0, static_cast<const uint4 *>(src), bytes / 16, d);
+        (void)hipEventRecord(a, 0);
+        for (int i = 0; i < 5; ++i)
+            hipLaunchKernelGGL(hbm_read, dim3(grid), dim3(256), 0, 0, static_cast<const uint4 *>(src), bytes / 16,
+                               d);
+        (void)hipEventRecord(b, 0);
+        if (hipEventSynchronize(b) != hipSuccess)
+            return 1;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        printf("%-40s %7.1f GB/s (4 GiB, 5 passes)\n", "HBM streaming read", 5.0 * bytes / ms / 1e6);
+        (void)hipFree(src);
+    }
+    {   // VALU
+        const int grid = cus * 8, iters = 20000;
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        hipLaunchKernelGGL(valu_bitop3, dim3(grid), dim3(256), 0, 0, d, 10);
+        (void)hipEventRecord(a, 0);
+        hipLaunchKernelGGL(valu_bitop3, dim3(grid), dim3(256), 0, 0, d, iters);
+        (void)hipEventRecord(b, 0);
+        if (hipEventSynchronize(b) != hipSuccess)
+            return 1;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        const double ops = (double)grid * 256 * iters * 8;
+        printf("%-40s %7.2f T ops/s\n", "v_bitop3_b32 (32-bit, per lane)", ops / ms / 1e9);
+    }
+    rc |= run<0, 1>("ds_read_b32 (4 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 2>("ds_read_b64 (8 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 4>("ds_read_b128 (16 B per lane)", d, p.multiProcessorCount);
     rc |= run<1, 4>("ds_write_b128 (16 B per lane)", d, p.multiProcessorCount);

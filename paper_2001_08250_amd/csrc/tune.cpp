@@ -117,7 +117,8 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
         }
     }
     for (uint32_t nw : {4u, 8u, 16u})
-    for (uint32_t fl : {2u << 8, 3u << 8, 4u << 8, PLAN_ROLLING, PLAN_ROLLING | (3u << 8)}) {
+    for (uint32_t fl : {2u << 8, 3u << 8, 4u << 8, PLAN_ROLLING, PLAN_ROLLING | (3u << 8), PLAN_PAIRS,
+                        PLAN_PAIRS | (3u << 8)}) {
         for (uint32_t t : {8u, 16u, 32u}) {
             if (t * nw > 8 * std::max<uint32_t>(B, 32))
                 continue;

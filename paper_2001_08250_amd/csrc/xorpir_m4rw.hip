@@ -278,6 +278,262 @@ void xorpir_m4rw_kernel(const WideArgs a)
     }
 }
 
+// ---- Paired 5-bucket tables -------------------------------------------
+//
+// A step covers 10 buckets ("pair" y: buckets 10y .. 10y+9) as two 5-bucket
+// tables A (10y .. 10y+4) and B (10y+5 .. 10y+9) of 32 x 1 KiB entries each.
+// Every request looks up both tables and folds the two entries into its
+// accumulator with one 3-input XOR per dword. Half of the waves load and build
+// table A, the other half table B, so each wave holds only 5 row slices per
+// pair in flight. Two sets of two tables (double buffering) fill 128 KiB of
+// LDS. Per request and pair: 2 address adds, 2 ds_read_b128 and 4 v_xor3 for
+// 10 x 4 units; one barrier per 10 buckets.
+constexpr int GP = 5;                       // buckets per table
+constexpr int EP = 1 << GP;                 // 32 entries
+constexpr int TABLEP_U4 = EP * 64;          // 32 KiB
+constexpr int SETP_U4 = 2 * TABLEP_U4;      // the two tables of a step
+constexpr int PAIR_BUCKETS = 2 * GP;
+
+// The 5 row slices of one half (0 = A, 1 = B) of pair y for this lane
+// (rows past n are readable padding and only meet zero request bits).
+__device__ __forceinline__ void load_half(uint4 (&d)[GP], const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                          uint32_t lane_off, uint64_t y, uint32_t half)
+{
+    const uint8_t *row = D + (y * PAIR_BUCKETS + half * GP) * row_bytes;
+#pragma unroll
+    for (int i = 0; i < GP; ++i) {
+        d[i] = *reinterpret_cast<const uint4 *>(row + lane_off);
+        row += row_bytes;
+    }
+}
+
+// Wave wt of the WPT waves that build one table writes entries (wt << LB) | x,
+// x < 2^LB, in Gray code order.
+template <int WPT>
+__device__ __forceinline__ void build_half(uint4 *__restrict__ tbl, const uint4 (&d)[GP], uint32_t wt, uint32_t lane)
+{
+    constexpr int LW = log2_waves<WPT>();
+    constexpr int LB = GP - LW;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int b = 0; b < LW; ++b)
+        if ((wt >> b) & 1u)
+            xor4(v, d[LB + b]);
+    uint4 *w = tbl + ((wt << LB) * 64u + lane);
+    w[0] = v;
+#pragma unroll
+    for (int k = 1; k < (1 << LB); ++k) {
+        xor4(v, d[__builtin_ctz(k)]);
+        w[(k ^ (k >> 1)) * 64] = v;
+    }
+}
+
+// a ^= b ^ c, one v_bitop3_b32 per dword (truth table 0x96 = x ^ y ^ z); the
+// compiler does not fuse the two XORs by itself here.
+__device__ __forceinline__ uint32_t xor3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return __builtin_amdgcn_bitop3_b32(x, y, z, 0x96);
+}
+
+__device__ __forceinline__ void xor3x4(uint4 &a, const uint4 &b, const uint4 &c)
+{
+    a.x = xor3(a.x, b.x, c.x);
+    a.y = xor3(a.y, b.y, c.y);
+    a.z = xor3(a.z, b.z, c.z);
+    a.w = xor3(a.w, b.w, c.w);
+}
+
+// Rolling pair lookups: off[r] holds table A's byte offset in its low half
+// and table B's (set-relative, so including the 32 KiB of table A) in its
+// high half.
+template <int TW, int INFL>
+__device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *set, const uint32_t (&off)[TW])
+{
+    uint4 ta[INFL], tb[INFL];
+#pragma unroll
+    for (int i = 0; i < INFL; ++i) {
+        ta[i] = *reinterpret_cast<const uint4 *>(set + (off[i] & 0xffffu));
+        tb[i] = *reinterpret_cast<const uint4 *>(set + (off[i] >> 16));
+    }
+#pragma unroll
+    for (int r = 0; r < TW; ++r) {
+        __builtin_amdgcn_sched_barrier(0);
+        xor3x4(acc[r], ta[r % INFL], tb[r % INFL]);
+        if (r + INFL < TW) {
+            ta[r % INFL] = *reinterpret_cast<const uint4 *>(set + (off[r + INFL] & 0xffffu));
+            tb[r % INFL] = *reinterpret_cast<const uint4 *>(set + (off[r + INFL] >> 16));
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Pair step for pair y, K = (y - first pair) mod U: ring[K % P] held this
+// wave's half of pair y (already built) and is refilled with pair y + P; the
+// half of pair y + 1 in ring[(K + 1) % P] is built into the other set; pair
+// y is looked up; the next pair's offsets are fetched; barrier.
+template <int NW, int TW, int P, int K>
+__device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW],
+                                          uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                          uint32_t lane_off, uint64_t y, const uint32_t *__restrict__ Qw,
+                                          uint32_t Bp, bool active, uint32_t half, uint32_t wt, uint32_t lane)
+{
+    constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
+    load_half(ring[slot], D, row_bytes, lane_off, y + P, half);
+    build_half<NW / 2>(lds + (buf ^ 1) * SETP_U4 + half * TABLEP_U4, ring[next], wt, lane);
+    if (active) {
+        lookup_pairs<TW, 4>(acc, reinterpret_cast<const uint8_t *>(lds + buf * SETP_U4 + lane), offs);
+        // the next pair's offsets (rows r0 .. r0 + TW - 1 < Bp of pair
+        // y + 1 <= pairs, inside the staging area); the index goes through
+        // readfirstlane for the reason given in group_step
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(y + 1));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((y + 1) >> 32));
+        const uint32_t *qn = Qw + (((uint64_t)hi << 32) | lo) * Bp;
+#pragma unroll
+        for (int i = 0; i < TW; ++i)
+            offs[i] = qn[i];
+    }
+    __syncthreads();
+}
+
+template <int NW, int TW, int P, int K, int U>
+__device__ __forceinline__ void pair_steps(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW], uint4 *lds,
+                                           const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
+                                           uint64_t y, const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
+                                           uint32_t half, uint32_t wt, uint32_t lane)
+{
+    if constexpr (K < U) {
+        pair_step<NW, TW, P, K>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt, lane);
+        pair_steps<NW, TW, P, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, y, Qw, Bp, active, half, wt,
+                                        lane);
+    }
+}
+
+template <int NW, int TW, int P, int K, int U>
+__device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW],
+                                                uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
+                                                uint32_t lane_off, uint64_t y, uint64_t left,
+                                                const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
+                                                uint32_t half, uint32_t wt, uint32_t lane)
+{
+    if constexpr (K < U) {
+        if ((uint64_t)K < left) {
+            pair_step<NW, TW, P, K>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt,
+                                    lane);
+            pair_steps_tail<NW, TW, P, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw, Bp,
+                                                 active, half, wt, lane);
+        }
+    }
+}
+
+// Same task layout and outputs as xorpir_m4rw_kernel; a.groups counts pairs.
+template <int NW, int TW, int P>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+void xorpir_m4rp_kernel(const WideArgs a)
+{
+    static_assert(NW >= 4 && NW <= 16, "two tables built by NW / 2 waves each");
+    constexpr int U = (P % 2 == 0) ? P : 2 * P;
+    __shared__ uint4 lds[2 * SETP_U4];
+    const uint32_t L = blockIdx.x;
+    const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
+    if (t >= a.n_rt * a.slices * a.splits)
+        return;
+    const uint32_t rt = t % a.n_rt;
+    const uint32_t rest = t / a.n_rt;
+    const uint32_t slice = rest % a.slices;
+    const uint32_t s = rest / a.slices;
+
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t half = wave / (NW / 2), wt = wave % (NW / 2);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t col = slice * 64u + lane;
+    const bool col_ok = col < a.stride16;
+    const uint32_t lane_off = (col_ok ? col : slice * 64u) * 16u;
+    const uint32_t r0 = rt * (NW * TW) + wave * TW;
+    const bool active = r0 < a.B;
+
+    const uint64_t gb = (uint64_t)s * a.groups_per_split;
+    const uint64_t ge = std::min<uint64_t>(a.groups, gb + a.groups_per_split);
+
+    uint4 acc[TW];
+#pragma unroll
+    for (int r = 0; r < TW; ++r)
+        acc[r] = make_uint4(0u, 0u, 0u, 0u);
+
+    if (gb < ge) {
+        uint4 ring[P][GP];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            load_half(ring[k], a.D, a.row_bytes, lane_off, gb + k, half);
+        const uint32_t *Qw = a.Qs + r0;
+        uint32_t offs[TW] = {};
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < TW; ++i)
+                offs[i] = Qw[gb * a.Bp + i];
+        }
+        build_half<NW / 2>(lds + half * TABLEP_U4, ring[0], wt, lane);
+        __syncthreads();
+        uint64_t y = gb;
+        for (; y + U <= ge; y += U)
+            pair_steps<NW, TW, P, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, Qw, a.Bp, active, half,
+                                        wt, lane);
+        if (y < ge)
+            pair_steps_tail<NW, TW, P, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, ge - y, Qw, a.Bp,
+                                             active, half, wt, lane);
+    }
+
+    if (active && col_ok) {
+        uint4 *o = reinterpret_cast<uint4 *>(a.out) + (uint64_t)s * a.out_split16 + col;
+#pragma unroll
+        for (int r = 0; r < TW; ++r)
+            if (r0 + r < a.B)
+                o[(uint64_t)(r0 + r) * a.out_row16] = acc[r];
+    }
+}
+
+// Qs[y * Bp + r] = (A << 16 ... ): for pair y and request row r, with a / b the
+// 5 request bits of tables A / B (bits >= n cleared), the low half holds
+// a * 1024 and the high half b * 1024 + 32 KiB (table B's offset within the
+// set). Rows B <= r < Bp and the extra pair y = pairs hold zero bits. One
+// thread per (chunk of 16 pairs, row): a chunk's 160 request bits are exactly
+// words 5c .. 5c+4 of the row.
+constexpr int PAIR_CHUNK = 16;
+
+__global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
+                                                                 uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
+                                                                 uint32_t Bp, uint64_t pairs)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t chunks = (pairs + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
+    const uint64_t c = t / Bp;
+    const uint32_t r = (uint32_t)(t % Bp);
+    if (c >= chunks)
+        return;
+    const uint64_t nwords = (n + 31) >> 5;
+    uint32_t w[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const uint64_t wi = c * 5 + j;
+        w[j] = (j < 5 && r < B && wi < nwords) ? Q[(uint64_t)r * qpitch_w + wi] : 0u;
+    }
+    const uint64_t y0 = c * PAIR_CHUNK;
+#pragma unroll
+    for (int k = 0; k < PAIR_CHUNK; ++k) {
+        const uint64_t y = y0 + k;
+        if (y > pairs)
+            break;
+        const int j = (PAIR_BUCKETS * k) >> 5, sh = (PAIR_BUCKETS * k) & 31;
+        const uint64_t win = (uint64_t)w[j] | ((uint64_t)w[j + 1] << 32);
+        uint32_t v = (uint32_t)(win >> sh) & ((1u << PAIR_BUCKETS) - 1u);
+        const uint64_t bit = y * PAIR_BUCKETS;
+        if (bit + PAIR_BUCKETS > n)
+            v &= bit >= n ? 0u : (1u << (n - bit)) - 1u;
+        const uint32_t ta = (v & (EP - 1)) * ENTRY_BYTES;
+        const uint32_t tb = (v >> GP) * ENTRY_BYTES + TABLEP_U4 * 16;
+        Qs[y * Bp + r] = (tb << 16) | ta;
+    }
+}
+
 // Qs[g * Bp + r] = (bits 6g .. 6g+5 of request row r, bits >= n cleared) *
 // ENTRY_BYTES; rows B <= r < Bp and the extra group g = groups are zero. One
 // thread per (chunk of 32 groups, row): the chunk's 192 request bits are
@@ -320,8 +576,9 @@ __global__ __launch_bounds__(256) void stage_wide_offsets_kernel(const uint32_t 
 
 using WideFn = void (*)(const WideArgs);
 
-// Prefetch depth comes from plan flags bits 8..11 (0 = 2 groups), the
-// lookup mode from bit 12 (PLAN_ROLLING).
+// Prefetch depth comes from plan flags bits 8..11 (0 = 2 steps), the
+// lookup mode from bit 12 (PLAN_ROLLING); bit 13 (PLAN_PAIRS) selects the
+// paired 5-bucket tables (rolling lookups always).
 WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
 {
     if (depth == 0)
@@ -345,8 +602,28 @@ WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
     return nullptr;
 }
 
+WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth)
+{
+    if (depth == 0)
+        depth = 2;
+    if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<4, 16, 2>;
+    if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<4, 32, 2>;
+    if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2>;
+    if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2>;
+    if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<8, 32, 2>;
+    if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rp_kernel<8, 32, 3>;
+    return nullptr;
+}
+
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
 uint32_t plan_mode(const Plan &p) { return (p.flags & PLAN_ROLLING) ? 1u : 0u; }
+bool plan_pairs(const Plan &p) { return (p.flags & PLAN_PAIRS) != 0; }
+
+WideFn plan_fn(const Plan &p)
+{
+    return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p))
+                         : wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
+}
 
 uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
@@ -354,15 +631,17 @@ uint32_t padded_rows(uint32_t B) { return (B + 63) & ~63u; }
 
 // Plan fields for this family: tile = requests per wave (TW), unroll = waves
 // per workgroup (NW).
-bool m4rw_plan_supported(const Plan &p)
+bool m4rw_plan_supported(const Plan &p) { return plan_fn(p) != nullptr; }
+
+// Table steps of a read: 6-bucket groups, or 10-bucket pairs.
+uint64_t m4rw_steps(uint64_t n, const Plan &p)
 {
-    return wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p)) != nullptr;
+    return plan_pairs(p) ? (n + PAIR_BUCKETS - 1) / PAIR_BUCKETS : (n + GB - 1) / GB;
 }
 
-uint64_t m4rw_staging_bytes(const ReadGeom &g)
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p)
 {
-    const uint64_t groups = (g.n + GB - 1) / GB;
-    return ((groups + 1) * padded_rows(g.B) * 4 + 255) & ~255ull;
+    return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * 4 + 255) & ~255ull;
 }
 
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
@@ -373,12 +652,10 @@ uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
     return ((g.B + R - 1) / R) * slices;
 }
 
-uint64_t m4rw_groups(uint64_t n) { return (n + GB - 1) / GB; }
-
 hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
                      hipEvent_t ee)
 {
-    WideFn fn = wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
+    WideFn fn = plan_fn(p);
     if (!fn)
         return hipErrorInvalidValue;
     WideArgs a{};
@@ -388,18 +665,24 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.slices = (a.stride16 + 63) / 64;
     a.B = g.B;
     a.Bp = padded_rows(g.B);
-    a.groups = m4rw_groups(g.n);
+    a.groups = m4rw_steps(g.n, p);
     uint32_t *qs = static_cast<uint32_t *>(partials);
     {
-        const uint64_t threads = (a.groups + 1 + STAGE_CHUNK - 1) / STAGE_CHUNK * a.Bp;
-        hipLaunchKernelGGL(stage_wide_offsets_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, stream,
-                           static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
+        const uint32_t chunk = plan_pairs(p) ? PAIR_CHUNK : STAGE_CHUNK;
+        const uint64_t threads = (a.groups + 1 + chunk - 1) / chunk * a.Bp;
+        const dim3 grid((uint32_t)((threads + 255) / 256));
+        if (plan_pairs(p))
+            hipLaunchKernelGGL(stage_pair_offsets_kernel, grid, dim3(256), 0, stream,
+                               static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
+        else
+            hipLaunchKernelGGL(stage_wide_offsets_kernel, grid, dim3(256), 0, stream,
+                               static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     a.Qs = qs;
-    partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g);
+    partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g, p);
     const uint32_t R = p.tile * p.unroll;
     a.n_rt = (g.B + R - 1) / R;
     a.splits = p.splits;

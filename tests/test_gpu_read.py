@@ -55,10 +55,11 @@ def test_small_workload_every_tile_schedule(kind):
 
 
 M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
-_R = pir.PLAN_ROLLING
+_R, _P = pir.PLAN_ROLLING, pir.PLAN_PAIRS
 # (waves, requests per wave, flags = prefetch depth << 8 | lookup mode)
 WIDE_SHAPES = [(4, 32, 2 << 8), (8, 16, 2 << 8), (8, 16, 4 << 8), (8, 32, 2 << 8), (8, 32, 3 << 8), (16, 16, 2 << 8),
-               (4, 8, _R), (4, 16, _R), (8, 8, _R), (8, 16, _R), (8, 16, _R | 3 << 8), (8, 32, _R), (16, 16, _R)]
+               (4, 8, _R), (4, 16, _R), (8, 8, _R), (8, 16, _R), (8, 16, _R | 3 << 8), (8, 32, _R), (16, 16, _R),
+               (4, 16, _P), (4, 32, _P), (8, 8, _P), (8, 16, _P), (8, 32, _P), (8, 32, _P | 3 << 8)]
 FOUR_RUSSIANS = ([(pir.KERNEL_M4R, (nw, tw, 0)) for nw, tw in M4R_SHAPES] +
                  [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES])
 
