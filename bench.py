@@ -352,6 +352,10 @@ def main():
     out = torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev)
     iv = torch.empty((IV_BITS // 8,), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    # The interest-vector fetch depends only on the published epoch, not on
+    # the read, so it goes out on a second stream (default priority) beside it.
+    iv_stream = torch.cuda.Stream(device=dev)
+    iv_sh = int(iv_stream.cuda_stream)
     L = pir.lib()
     sh = int(stream.cuda_stream)
 
@@ -384,7 +388,8 @@ def main():
         db.read_async(q, out)
         host_s["read_call"] += time.perf_counter() - t
         if full:
-            L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), sh)
+            rc = L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), iv_sh)
+            assert rc == 0, rc
 
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
