@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--masked", action="store_true",
+                    help="serialized PIR: every answer XORed with a ChaCha20 one-time mask from a per-request seed")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
                     help="no GPU: turn two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of a bench run "
                          "made with --calib-copy-mib into profiles/traffic_<workload>.json")
@@ -349,6 +351,8 @@ def main():
 
     dev = torch.device("cuda:0")
     q = torch.from_numpy(req).to(dev)
+    seeds = synth.uniform_bytes(w.req_seed + 99, B * 32).reshape(B, 32) if args.masked else None
+    seeds_dev = torch.from_numpy(seeds).to(dev) if args.masked else None
     out = torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev)
     iv = torch.empty((IV_BITS // 8,), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -385,7 +389,10 @@ def main():
         if full:
             do_writes(k)
         t = time.perf_counter()
-        db.read_async(q, out)
+        if seeds_dev is not None:
+            db.read_masked_async(q, seeds_dev, out)
+        else:
+            db.read_async(q, out)
         host_s["read_call"] += time.perf_counter() - t
         if full:
             rc = L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), iv_sh)
@@ -460,7 +467,8 @@ def main():
                     D[int(wr[1][i])] = wr[3][i]
         rows = np.arange(min(args.cpu_rows, B))
         t1 = time.perf_counter()
-        want = oracle.pir_read(D, req[rows], threads=threads)
+        want = (oracle.pir_read_masked(D, req[rows], seeds[rows], threads=threads) if args.masked
+                else oracle.pir_read(D, req[rows], threads=threads))
         dt = time.perf_counter() - t1
         parity = bool(np.array_equal(want, got[rows]))
         if full:
@@ -487,7 +495,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "B": B,
-                   "step": "writes+commit+read+interest" if full else "read",
+                   "step": ("writes+commit+read+interest" if full else "read") + (" (masked)" if args.masked else ""),
                    "writes_per_step": nw,
                    "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll,
                             "flags": plan.flags},

@@ -151,6 +151,41 @@ int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req_pitch,
                           void *d_resp, uint64_t resp_pitch, const uint64_t *resp_first,
                           void *hip_stream);
 
+/* ---------------------------------------------------------- serialized PIR */
+
+/*
+ * Serialized PIR (section "Serialized PIR", steps 6 and 7): the server answers
+ * each request with its IT-PIR answer XORed with a one-time mask of the
+ * answer's size, P = PRNG(p), p being the request's seed. The paper leaves
+ * the PRNG open; here it is ChaCha20 (D. J. Bernstein, in the form of
+ * RFC 8439): the 32-byte seed is the key, the 96-bit nonce is zero, the
+ * 32-bit block counter starts at 0, and P is the first d * msg_bytes bytes
+ * of the keystream:
+ *
+ *     resp[r] = (XOR of the buckets selected by req[r]) XOR P(seeds[r]).
+ *
+ *   seeds: B seeds of 32 bytes, row-major (host memory for the synchronous
+ *          call; device memory, 4-byte aligned, for the async one).
+ * Every other argument, the validation and the stream rules are those of
+ * pir_read_batch / pir_read_batch_async; NULL seeds with B > 0 -> PIR_EINVAL.
+ * A seed must not be used for two answers (the mask is a one-time pad).
+ */
+int pir_read_batch_masked(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint8_t *seeds, uint8_t *resp);
+int pir_read_batch_masked_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B,
+                                const void *d_seeds, void *d_resp, uint64_t resp_pitch, void *hip_stream);
+
+/*
+ * The leader's combination (section "Serialized PIR", step 8): row r of
+ * d_out = XOR over i < l of row r of d_in[i], row_bytes bytes per row, on the
+ * given stream. d_in is a host array of l device pointers (1 <= l <= 16);
+ * rows start at d_in[i] + r * in_pitch and d_out + r * out_pitch. Requires
+ * row_bytes, both pitches and every pointer to be multiples of 16 and pitches
+ * >= row_bytes (PIR_EINVAL otherwise). B = 0 is a no-op. No handle: the work
+ * runs on the current HIP device.
+ */
+int pir_xor_combine_async(void *d_out, uint64_t out_pitch, const void *const *d_in, uint32_t l,
+                          uint64_t in_pitch, uint32_t B, uint64_t row_bytes, void *hip_stream);
+
 /* --------------------------------------------------------- kernel schedule */
 
 /* Kernel families of the read path. */

@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline may import this package; the library under ``paper_2001_08250_amd``
 never does, and this package never imports the library. It wraps the plain C
-definitions in ``pir_oracle.c`` and ``cuckoo_oracle.c`` (built with gcc by
-:func:`build`) through ctypes.
+definitions in ``pir_oracle.c``, ``cuckoo_oracle.c`` and ``mask_oracle.c`` (built
+with gcc by :func:`build`) through ctypes.
 
 * :func:`pir_read` -- the server answer of IT-PIR (section "Background: PIR",
   server step; appendix "Security Proofs", answer functions): for each request
@@ -15,6 +15,10 @@ definitions in ``pir_oracle.c`` and ``cuckoo_oracle.c`` (built with gcc by
   in the last ``window`` epochs (section "Private Notifications").
 * :func:`splitmix64` -- SplitMix64 stream (Steele, Lea, Flood 2014), the
   randomness the cuckoo walk draws from the shared seed.
+* :func:`pir_read_masked`, :func:`apply_masks`, :func:`chacha20_stream` --
+  serialized PIR (section "Serialized PIR"): each answer XORed with a one-time
+  mask drawn from a per-request seed; the PRNG is read as ChaCha20 (RFC 8439
+  form, seed as key, zero nonce, counter from 0).
 """
 from __future__ import annotations
 
@@ -25,7 +29,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["pir_oracle.c", "cuckoo_oracle.c"]
+_SOURCES = ["pir_oracle.c", "cuckoo_oracle.c", "mask_oracle.c"]
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
 
@@ -78,6 +82,10 @@ def _load():
     lib.oracle_interest_window.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32), u64p,
                                            ctypes.c_uint32, ctypes.c_uint32, u8p]
     lib.oracle_interest_window.restype = ctypes.c_int
+    lib.oracle_chacha20_stream.argtypes = [u8p, u8p, ctypes.c_uint32, u8p, ctypes.c_uint64]
+    lib.oracle_chacha20_stream.restype = None
+    lib.oracle_apply_masks.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, u8p]
+    lib.oracle_apply_masks.restype = None
     _lib = lib
     return lib
 
@@ -201,3 +209,32 @@ def interest_window(m_bits: int, epochs: list, last: int, window: int) -> np.nda
     if rc != 0:
         raise ValueError("interest position out of range")
     return out
+
+
+def chacha20_stream(key: bytes, nonce: bytes, counter: int, nbytes: int) -> np.ndarray:
+    """nbytes of ChaCha20 keystream (32-byte key, 12-byte nonce, first block counter)."""
+    k = np.frombuffer(bytes(key), dtype=np.uint8).copy()
+    iv = np.frombuffer(bytes(nonce), dtype=np.uint8).copy()
+    if k.size != 32 or iv.size != 12:
+        raise ValueError("key must be 32 bytes and nonce 12 bytes")
+    out = np.zeros(nbytes, dtype=np.uint8)
+    _load().oracle_chacha20_stream(_ptr(k), _ptr(iv), counter, _ptr(out), nbytes)
+    return out
+
+
+def apply_masks(resp: np.ndarray, seeds: np.ndarray) -> np.ndarray:
+    """resp[r] XOR P(seeds[r]) (section "Serialized PIR", steps 6-7 and 9): the
+    mask is the first row-length bytes of the ChaCha20 keystream keyed by the
+    32-byte seed, zero nonce, counter from 0. Returns a new array."""
+    out = np.ascontiguousarray(resp, dtype=np.uint8).copy()
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint8).reshape(-1, 32)
+    if out.ndim != 2 or seeds.shape[0] != out.shape[0]:
+        raise ValueError("one 32-byte seed per response row")
+    _load().oracle_apply_masks(_ptr(out), out.shape[1], out.shape[0], _ptr(seeds))
+    return out
+
+
+def pir_read_masked(D: np.ndarray, req: np.ndarray, seeds: np.ndarray, n: int | None = None,
+                    threads: int = 1) -> np.ndarray:
+    """A serialized-PIR server's answers: pir_read(D, req) XOR the one-time masks."""
+    return apply_masks(pir_read(D, req, n=n, threads=threads), seeds)

@@ -95,6 +95,9 @@ SIGNATURES = {
     "pir_read_batch": (ctypes.c_int, [_vp, _u8p, _u32, _u8p]),
     "pir_read_batch_async": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp, _u64, _vp]),
     "pir_read_stream_async": (ctypes.c_int, [_vp, _vp, _u64, _u32p, _u64p, _u32, _vp, _u64, _u64p, _vp]),
+    "pir_read_batch_masked": (ctypes.c_int, [_vp, _u8p, _u32, _u8p, _u8p]),
+    "pir_read_batch_masked_async": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp, _vp, _u64, _vp]),
+    "pir_xor_combine_async": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(_vp), _u32, _u64, _u32, _u64, _vp]),
     "pir_set_plan": (ctypes.c_int, [_vp, ctypes.POINTER(pir_plan)]),
     "pir_get_plan": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(pir_plan)]),
     "pir_tune": (ctypes.c_int, [_vp, _u32, _u32, ctypes.POINTER(pir_plan), ctypes.POINTER(ctypes.c_double)]),
@@ -174,6 +177,18 @@ def __getattr__(name):  # raw C entry points under their own names
     if name in SIGNATURES:
         return getattr(lib(), name)
     raise AttributeError(name)
+
+
+def xor_combine_async(out, ins, stream=None):
+    """Leader combine: out[r] = XOR of ins[i][r] (device uint8 tensors [B, row_bytes])."""
+    B, row = out.shape
+    ptrs = (ctypes.c_void_p * len(ins))(*[t.data_ptr() for t in ins])
+    op = out.stride(0) if B > 1 else row
+    ip = ins[0].stride(0) if B > 1 else row
+    if any(t.stride(0) != ins[0].stride(0) or tuple(t.shape) != (B, row) for t in ins):
+        raise ValueError("inputs must share shape and row pitch")
+    _check(lib().pir_xor_combine_async(out.data_ptr(), op, ptrs, len(ins), ip, B, row, _stream_handle(stream)),
+           "pir_xor_combine_async")
 
 
 def _stream_handle(stream=None) -> int:
@@ -259,6 +274,34 @@ class PirDB:
         op = resp.stride(0) if B > 1 else resp.shape[1]
         _check(self._L.pir_read_batch_async(self.h, req.data_ptr(), rp, B, resp.data_ptr(), op,
                                             _stream_handle(stream)), "pir_read_batch_async")
+
+    def read_masked(self, req: np.ndarray, seeds: np.ndarray) -> np.ndarray:
+        """Serialized-PIR answers: each row XOR the one-time mask of its 32-byte seed."""
+        req = np.ascontiguousarray(req, dtype=np.uint8)
+        if req.ndim == 1:
+            req = req.reshape(1, -1)
+        if req.shape[1] != self.req_bytes:
+            raise ValueError(f"request rows must be {self.req_bytes} bytes")
+        B = req.shape[0]
+        seeds = np.ascontiguousarray(seeds, dtype=np.uint8).reshape(-1, 32)
+        if seeds.shape[0] != B:
+            raise ValueError("one 32-byte seed per request")
+        resp = np.empty((B, self.bucket_bytes), dtype=np.uint8)
+        if B:
+            _check(self._L.pir_read_batch_masked(self.h, _ptr(req), B, _ptr(seeds), _ptr(resp)),
+                   "pir_read_batch_masked")
+        return resp
+
+    def read_masked_async(self, req, seeds, resp, stream=None):
+        """Device tensors: req [B, >= req_bytes], seeds uint8 [B, 32] (contiguous), resp [B, >= bucket_bytes]."""
+        B = req.shape[0]
+        rp = req.stride(0) if B > 1 else req.shape[1]
+        op = resp.stride(0) if B > 1 else resp.shape[1]
+        if tuple(seeds.shape) != (B, 32) or not seeds.is_contiguous():
+            raise ValueError("seeds must be a contiguous [B, 32] uint8 tensor")
+        _check(self._L.pir_read_batch_masked_async(self.h, req.data_ptr(), rp, B, seeds.data_ptr(),
+                                                   resp.data_ptr(), op, _stream_handle(stream)),
+               "pir_read_batch_masked_async")
 
     def read_stream_async(self, req, sizes, resp, req_first=None, resp_first=None, stream=None):
         sizes = np.ascontiguousarray(sizes, dtype=np.uint32)

@@ -25,6 +25,7 @@ SOURCES = [
     "tune.cpp",
     "stream.cpp",
     "serve.cpp",
+    "mask.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value", f"-I{os.path.join(ROOT, 'include')}"]

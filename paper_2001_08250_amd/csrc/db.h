@@ -23,8 +23,10 @@ struct Scratch {
     uint64_t resp_cap = 0;
     void *part = nullptr;
     uint64_t part_cap = 0;
-    void *aux = nullptr;      // persistent-queue tables and counters
+    void *aux = nullptr;      // stream index lists and gathered rows
     uint64_t aux_cap = 0;
+    void *keys = nullptr;     // mask seeds of a synchronous masked read
+    uint64_t keys_cap = 0;
     hipGraphExec_t exec = nullptr;  // captured stream read
     std::vector<uint64_t> sig;      // what the captured graph bakes in
 };

@@ -31,6 +31,9 @@ struct ReadGeom {
     uint32_t B;
     void *out;
     uint64_t out_pitch;
+    // serialized PIR: B x 8 key words (32-byte seeds) of the answers'
+    // one-time masks, or none
+    const uint32_t *keys = nullptr;
 };
 
 struct Plan {
@@ -93,6 +96,25 @@ hipError_t launch_gather_rows(void *dst, uint64_t dst_pitch, const void *src, ui
 
 // --- interest vector -----------------------------------------------------
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);           // bytes % 4 == 0
+// The last step of a read: XOR the bucket splits' partials into the response
+// rows (splits > 1), and apply the one-time masks when g.keys is set (fused
+// into that reduction, or in place on the rows when there were no splits).
+hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream);
+hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                            uint64_t out_pitch, const uint32_t *keys, hipStream_t stream);
+
+// Leader combine (serialized PIR): out row r = XOR of the l input rows r.
+constexpr uint32_t COMBINE_MAX = 16;
+struct CombineArgs {
+    uint4 *out;
+    uint64_t out_row16;
+    const uint4 *in[COMBINE_MAX];
+    uint64_t in_row16;
+    uint32_t l, B;
+    uint64_t row16;
+};
+hipError_t launch_xor_combine(const CombineArgs &a, hipStream_t stream);
+
 // Epoch commit, device half (one launch): staged rows into the back copy and
 // the interest-vector update (see commit_kernel).
 struct CommitArgs {

@@ -252,6 +252,7 @@ void free_db(pir_db *db)
         hipFree(kv.second.resp);
         hipFree(kv.second.part);
         hipFree(kv.second.aux);
+        hipFree(kv.second.keys);
     }
     for (int b = 0; b < 2; ++b) {
         for (auto &kv : db->readers[b])
@@ -578,14 +579,10 @@ static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
     return PIR_OK;
 }
 
-int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp)
+// Synchronous read (host rows in and out); seeds = B x 32 bytes of mask
+// seeds, or NULL for the plain answers.
+static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint8_t *seeds, uint8_t *resp)
 {
-    if (!db)
-        return PIR_EINVAL;
-    if (B == 0)
-        return PIR_OK;
-    if (!req_bits || !resp)
-        return PIR_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     HIP_TRY(hipSetDevice(db->device));
     Scratch &sc = scratch_for(db, db->stream);
@@ -594,6 +591,11 @@ int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *res
     HIP_TRY(hipMemcpy2DAsync(sc.req, db->qpitch, req_bits, db->qbytes, db->qbytes, B, hipMemcpyHostToDevice,
                              db->stream));
     ReadGeom g = read_geom(db, sc.req, db->qpitch, B, sc.resp, db->stride);
+    if (seeds) {
+        PIR_TRY(ensure_device(&sc.keys, &sc.keys_cap, (uint64_t)B * 32));
+        HIP_TRY(hipMemcpyAsync(sc.keys, seeds, (uint64_t)B * 32, hipMemcpyHostToDevice, db->stream));
+        g.keys = static_cast<const uint32_t *>(sc.keys);
+    }
     Plan p = choose_plan(db, B);
     PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
     hipEvent_t eb, ee;
@@ -605,15 +607,11 @@ int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *res
     return PIR_OK;
 }
 
-int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B, void *d_resp,
-                         uint64_t resp_pitch, void *hip_stream)
+// Stream-ordered read of device rows; d_keys = B x 8 key words on the device
+// (4-byte aligned), or NULL.
+static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B, const void *d_keys,
+                      void *d_resp, uint64_t resp_pitch, void *hip_stream)
 {
-    if (!db)
-        return PIR_EINVAL;
-    if (B == 0)
-        return PIR_OK;
-    if (!d_req || !d_resp || req_pitch < db->qbytes || resp_pitch < db->bucket_bytes)
-        return PIR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     HIP_TRY(hipSetDevice(db->device));
@@ -639,6 +637,7 @@ int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint
         op = db->stride;
     }
     ReadGeom g = read_geom(db, q, qp, B, out, op);
+    g.keys = static_cast<const uint32_t *>(d_keys);
     Plan p = choose_plan(db, B);
     PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
     hipEvent_t eb, ee;
@@ -648,6 +647,78 @@ int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint
         HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,
                                  hipMemcpyDeviceToDevice, s));
     return note_reader(db, db->front, s);
+}
+
+int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!req_bits || !resp)
+        return PIR_EINVAL;
+    return read_sync(db, req_bits, B, nullptr, resp);
+}
+
+int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B, void *d_resp,
+                         uint64_t resp_pitch, void *hip_stream)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!d_req || !d_resp || req_pitch < db->qbytes || resp_pitch < db->bucket_bytes)
+        return PIR_EINVAL;
+    return read_async(db, d_req, req_pitch, B, nullptr, d_resp, resp_pitch, hip_stream);
+}
+
+int pir_read_batch_masked(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint8_t *seeds, uint8_t *resp)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!req_bits || !seeds || !resp)
+        return PIR_EINVAL;
+    return read_sync(db, req_bits, B, seeds, resp);
+}
+
+int pir_read_batch_masked_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B, const void *d_seeds,
+                                void *d_resp, uint64_t resp_pitch, void *hip_stream)
+{
+    if (!db)
+        return PIR_EINVAL;
+    if (B == 0)
+        return PIR_OK;
+    if (!d_req || !d_seeds || !d_resp || req_pitch < db->qbytes || resp_pitch < db->bucket_bytes ||
+        (reinterpret_cast<uintptr_t>(d_seeds) & 3))
+        return PIR_EINVAL;
+    return read_async(db, d_req, req_pitch, B, d_seeds, d_resp, resp_pitch, hip_stream);
+}
+
+int pir_xor_combine_async(void *d_out, uint64_t out_pitch, const void *const *d_in, uint32_t l, uint64_t in_pitch,
+                          uint32_t B, uint64_t row_bytes, void *hip_stream)
+{
+    if (B == 0)
+        return PIR_OK;
+    if (!d_out || !d_in || l == 0 || l > COMBINE_MAX || row_bytes == 0 || (row_bytes & 15) ||
+        out_pitch < row_bytes || in_pitch < row_bytes || (out_pitch & 15) || (in_pitch & 15) ||
+        (reinterpret_cast<uintptr_t>(d_out) & 15))
+        return PIR_EINVAL;
+    CombineArgs a{};
+    a.out = static_cast<uint4 *>(d_out);
+    a.out_row16 = out_pitch / 16;
+    for (uint32_t i = 0; i < l; ++i) {
+        if (!d_in[i] || (reinterpret_cast<uintptr_t>(d_in[i]) & 15))
+            return PIR_EINVAL;
+        a.in[i] = static_cast<const uint4 *>(d_in[i]);
+    }
+    a.in_row16 = in_pitch / 16;
+    a.l = l;
+    a.B = B;
+    a.row16 = row_bytes / 16;
+    HIP_TRY(launch_xor_combine(a, static_cast<hipStream_t>(hip_stream)));
+    return PIR_OK;
 }
 
 int pir_set_plan(pir_db *db, const pir_plan *plan)

@@ -114,16 +114,32 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
     return p;
 }
 
+hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                             uint64_t out_pitch, hipStream_t stream);
+
+hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream)
+{
+    if (g.keys)
+        return launch_mask_rows(partials, splits, g.B, g.stride, g.out, g.out_pitch, g.keys, stream);
+    return launch_xor_splits(partials, splits, g.B, g.stride, g.out, g.out_pitch, stream);
+}
+
 hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t ev_begin,
                        hipEvent_t ev_end)
 {
     if (g.B == 0)
         return hipSuccess;
+    hipError_t e;
     if (p.kind == KIND_M4R)
-        return launch_m4r_read(g, p, partials, stream, ev_begin, ev_end);
-    if (p.kind == KIND_M4RW)
-        return launch_m4rw_read(g, p, partials, stream, ev_begin, ev_end);
-    return launch_tile_read(g, p, partials, stream, ev_begin, ev_end);
+        e = launch_m4r_read(g, p, partials, stream, ev_begin, ev_end);
+    else if (p.kind == KIND_M4RW)
+        e = launch_m4rw_read(g, p, partials, stream, ev_begin, ev_end);
+    else
+        e = launch_tile_read(g, p, partials, stream, ev_begin, ev_end);
+    // without splits the kernel wrote the plain answers: mask them in place
+    if (e == hipSuccess && g.keys && p.splits <= 1)
+        e = launch_mask_rows(nullptr, 0, g.B, g.stride, g.out, g.out_pitch, g.keys, stream);
+    return e;
 }
 
 }  // namespace talek

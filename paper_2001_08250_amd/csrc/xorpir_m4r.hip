@@ -280,7 +280,7 @@ hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hip
         e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
-    return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);
+    return launch_split_reduce(partials, p.splits, g, stream);
 }
 
 }  // namespace talek

@@ -298,7 +298,7 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
         e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
-    return launch_xor_splits(partials, p.splits, g.B, g.stride, g.out, g.out_pitch, stream);
+    return launch_split_reduce(partials, p.splits, g, stream);
 }
 
 }  // namespace talek

@@ -37,6 +37,16 @@ def test_validation_without_device():
     assert L.pir_read_batch(None, None, 0, None) == pir.PIR_EINVAL
     assert L.pir_epoch_commit(None, None) == pir.PIR_EINVAL
     assert L.pir_cuckoo_create(None, 0, 0, 500, ctypes.byref(h)) == pir.PIR_EINVAL
+    assert L.pir_read_batch_masked(None, None, 0, None, None) == pir.PIR_EINVAL
+    assert L.pir_read_batch_masked_async(None, None, 0, 0, None, None, 0, None) == pir.PIR_EINVAL
+    two = (ctypes.c_void_p * 2)(16, 32)
+    assert L.pir_xor_combine_async(None, 16, two, 2, 16, 0, 16, None) == pir.PIR_OK   # B = 0: no-op
+    assert L.pir_xor_combine_async(None, 16, two, 2, 16, 1, 16, None) == pir.PIR_EINVAL
+    assert L.pir_xor_combine_async(16, 16, two, 0, 16, 1, 16, None) == pir.PIR_EINVAL  # l = 0
+    many = (ctypes.c_void_p * 17)(*([16] * 17))
+    assert L.pir_xor_combine_async(16, 16, many, 17, 16, 1, 16, None) == pir.PIR_EINVAL  # l > 16
+    assert L.pir_xor_combine_async(16, 16, two, 2, 16, 1, 24, None) == pir.PIR_EINVAL  # row % 16
+    assert L.pir_xor_combine_async(16, 8, two, 2, 16, 1, 16, None) == pir.PIR_EINVAL   # pitch < row
     assert L.pir_profile_enable(None, 1) == pir.PIR_EINVAL
     assert L.pir_profile_collect(None, None, 0, None) == pir.PIR_EINVAL
     L.pir_db_destroy(None)  # NULL-safe
