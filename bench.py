@@ -421,6 +421,17 @@ def main():
     wall = time.perf_counter() - t0
     kern = db.profile_collect()
     db.profile_enable(False)
+    codec = None
+    if full:
+        # GetUpdates payloads (not timed above): the published global vector and
+        # the latest epoch's delta, raw and compressed, and the encode time
+        t1 = time.perf_counter()
+        g_bytes = len(db.interest_encoded())
+        t_enc = time.perf_counter() - t1
+        e_last = int(L.pir_epoch(db.h))
+        codec = {"raw_bytes": IV_BITS // 8, "global_encoded_bytes": g_bytes,
+                 "delta_encoded_bytes": len(db.interest_encoded(e_last)),
+                 "global_encode_ms": round(1e3 * t_enc, 3)}
     assert kern.size == min(K, pir.PROFILE_MAX)
     kern_ms = float(np.mean(kern))
     got = out.cpu().numpy()
@@ -504,6 +515,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_sampled": parity,
         "host_ms_per_step": {key: round(1e3 * v / K, 4) for key, v in host_s.items()},
+        "interest_codec": codec,
     }
     print(json.dumps(line), flush=True)
     db.close()

@@ -282,6 +282,28 @@ int pir_interest_vector(pir_db *db, uint8_t *out, uint64_t out_bytes);
 /* Device-memory variant of pir_interest_vector, stream-ordered. */
 int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void *hip_stream);
 
+/*
+ * Compressed interest vectors for GetUpdates (section "Private
+ * Notifications": clients fetch compressed Bloom-filter deltas and keep a
+ * window of them). The paper fixes no format; the stream is, little-endian:
+ *   bytes 0-7 m, bytes 8-15 c (bits set), bytes 16-19 the Rice parameter
+ *   k = floor(log2(max(1, floor(m / (c + 1))))), bytes 20-23 zero, then for
+ *   the set positions p_0 < ... < p_{c-1} (p_{-1} = -1) the gaps
+ *   g = p_i - p_{i-1} - 1, each as floor(g / 2^k) one-bits, one zero-bit and
+ *   the k low bits of g least significant first, packed into bytes least
+ *   significant bit first (Golomb-Rice coding).
+ * pir_interest_vector_encoded encodes the published global vector;
+ * pir_interest_delta_encoded the delta of published epoch `epoch` (the
+ * interest bits added before that commit), which must still be in the
+ * window: pir_epoch(db) - window < epoch <= pir_epoch(db), else PIR_ERANGE.
+ * *out_bytes receives the stream length; out may be NULL to ask for it. If
+ * out_cap is smaller than the stream, PIR_EINVAL (with *out_bytes set).
+ * Synchronous, ordered after the handle's commits. PIR_EINVAL if the vector
+ * has 2^31 or more bits set.
+ */
+int pir_interest_vector_encoded(pir_db *db, uint8_t *out, uint64_t out_cap, uint64_t *out_bytes);
+int pir_interest_delta_encoded(pir_db *db, uint64_t epoch, uint8_t *out, uint64_t out_cap, uint64_t *out_bytes);
+
 /* ------------------------------------------------- server cuckoo table */
 
 /*

@@ -19,6 +19,9 @@ with gcc by :func:`build`) through ctypes.
   serialized PIR (section "Serialized PIR"): each answer XORed with a one-time
   mask drawn from a per-request seed; the PRNG is read as ChaCha20 (RFC 8439
   form, seed as key, zero nonce, counter from 0).
+* :func:`iv_encode`, :func:`iv_decode` -- the compressed interest-vector
+  stream (Golomb-Rice coded gaps between set bits; section "Private
+  Notifications": clients fetch compressed Bloom-filter deltas).
 """
 from __future__ import annotations
 
@@ -29,7 +32,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["pir_oracle.c", "cuckoo_oracle.c", "mask_oracle.c"]
+_SOURCES = ["pir_oracle.c", "cuckoo_oracle.c", "mask_oracle.c", "codec_oracle.c"]
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
 
@@ -86,6 +89,10 @@ def _load():
     lib.oracle_chacha20_stream.restype = None
     lib.oracle_apply_masks.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint32, u8p]
     lib.oracle_apply_masks.restype = None
+    lib.oracle_iv_encode.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64]
+    lib.oracle_iv_encode.restype = ctypes.c_uint64
+    lib.oracle_iv_decode.argtypes = [u8p, ctypes.c_uint64, u8p, ctypes.c_uint64]
+    lib.oracle_iv_decode.restype = ctypes.c_uint64
     _lib = lib
     return lib
 
@@ -238,3 +245,28 @@ def pir_read_masked(D: np.ndarray, req: np.ndarray, seeds: np.ndarray, n: int | 
                     threads: int = 1) -> np.ndarray:
     """A serialized-PIR server's answers: pir_read(D, req) XOR the one-time masks."""
     return apply_masks(pir_read(D, req, n=n, threads=threads), seeds)
+
+
+def iv_encode(v: np.ndarray, m: int) -> bytes:
+    """Compressed stream of an m-bit vector (uint8, ceil(m/8) bytes, LSB-first)."""
+    v = np.ascontiguousarray(v, dtype=np.uint8).reshape(-1)
+    if v.size < (m + 7) // 8:
+        raise ValueError("vector shorter than m bits")
+    lib = _load()
+    size = lib.oracle_iv_encode(_ptr(v), m, None, 0)
+    out = np.zeros(size, dtype=np.uint8)
+    lib.oracle_iv_encode(_ptr(v), m, _ptr(out), size)
+    return out.tobytes()
+
+
+def iv_decode(stream: bytes) -> tuple[int, np.ndarray]:
+    """(m, vector) from a compressed stream; ValueError if it is malformed."""
+    s = np.frombuffer(bytes(stream), dtype=np.uint8).copy()
+    if s.size < 24:
+        raise ValueError("stream shorter than its header")
+    m = int(s[:8].view(np.uint64)[0])
+    v = np.zeros((m + 7) // 8, dtype=np.uint8)
+    got = _load().oracle_iv_decode(_ptr(s), s.size, _ptr(v), v.size)
+    if got != m:
+        raise ValueError("malformed stream")
+    return m, v

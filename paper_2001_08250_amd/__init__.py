@@ -110,6 +110,8 @@ SIGNATURES = {
     "pir_interest_add": (ctypes.c_int, [_vp, _u32p, _u32]),
     "pir_interest_vector": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_interest_vector_async": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
+    "pir_interest_vector_encoded": (ctypes.c_int, [_vp, _u8p, _u64, _u64p]),
+    "pir_interest_delta_encoded": (ctypes.c_int, [_vp, _u64, _u8p, _u64, _u64p]),
     "pir_cuckoo_create": (ctypes.c_int, [_vp, _u64, _u64, _u32, ctypes.POINTER(_vp)]),
     "pir_cuckoo_create_detached": (ctypes.c_int, [_u64, _u32, _u32, _u64, _u64, _u32, ctypes.POINTER(_vp)]),
     "pir_cuckoo_destroy": (None, [_vp]),
@@ -347,6 +349,19 @@ class PirDB:
     def interest_add(self, pos):
         pos = np.ascontiguousarray(pos, dtype=np.uint32).reshape(-1)
         _check(self._L.pir_interest_add(self.h, _ptr(pos, ctypes.c_uint32), pos.size), "pir_interest_add")
+
+    def interest_encoded(self, epoch: int | None = None) -> bytes:
+        """Compressed stream of the global vector (epoch None) or of a published
+        epoch's delta still in the window."""
+        size = ctypes.c_uint64(0)
+        if epoch is None:
+            call = lambda buf, cap: self._L.pir_interest_vector_encoded(self.h, buf, cap, ctypes.byref(size))
+        else:
+            call = lambda buf, cap: self._L.pir_interest_delta_encoded(self.h, epoch, buf, cap, ctypes.byref(size))
+        _check(call(None, 0), "interest_encoded (size)")
+        out = np.zeros(size.value, dtype=np.uint8)
+        _check(call(_ptr(out), out.size), "interest_encoded")
+        return out.tobytes()
 
     def interest_vector(self) -> np.ndarray:
         m = getattr(self, "m_bits", IV_DEFAULT_BITS)

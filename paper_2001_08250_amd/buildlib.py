@@ -26,6 +26,7 @@ SOURCES = [
     "stream.cpp",
     "serve.cpp",
     "mask.hip",
+    "iv_codec.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value", f"-I{os.path.join(ROOT, 'include')}"]

@@ -104,6 +104,9 @@ struct pir_db {
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     size_t prof_used = 0;
+    // compressed interest vectors: device scratch of the encoder
+    void *codec = nullptr, *codec2 = nullptr, *codec3 = nullptr;
+    uint64_t codec_cap = 0, codec2_cap = 0, codec3_cap = 0;
     uint64_t mirror_idx_cap = 0;
 };
 
@@ -114,6 +117,10 @@ Plan choose_plan(pir_db *db, uint32_t B);
 ReadGeom read_geom(pir_db *db, const void *q, uint64_t qpitch, uint32_t B, void *out, uint64_t out_pitch);
 // Scratch of a stream (created on first use).
 Scratch &scratch_for(pir_db *db, hipStream_t s);
+// Compressed stream of the m-bit device vector `words` into host memory (out
+// may be NULL: size only); stream-ordered on s, returns when done.
+int encode_interest(pir_db *db, const uint32_t *words, uint64_t m, uint8_t *out, uint64_t cap, uint64_t *out_bytes,
+                    hipStream_t s);
 // Record that stream s reads buffer b (commits wait for it before reusing b).
 int note_reader(pir_db *db, int b, hipStream_t s);
 // Tuning table lookup: true and *p if an entry exists for (n, B class, stride).

@@ -274,6 +274,9 @@ void free_db(pir_db *db)
             hipEventDestroy(db->upload_ev[i]);
     if (db->mirror_idx_host)
         hipHostFree(db->mirror_idx_host);
+    hipFree(db->codec);
+    hipFree(db->codec2);
+    hipFree(db->codec3);
     for (auto &ev : db->prof_ev) {
         hipEventDestroy(ev.first);
         hipEventDestroy(ev.second);
@@ -790,6 +793,27 @@ int pir_interest_vector(pir_db *db, uint8_t *out, uint64_t out_bytes)
     HIP_TRY(hipMemcpyAsync(out, db->iv_global[db->front], bytes, hipMemcpyDeviceToHost, db->stream));
     HIP_TRY(hipStreamSynchronize(db->stream));
     return PIR_OK;
+}
+
+int pir_interest_vector_encoded(pir_db *db, uint8_t *out, uint64_t out_cap, uint64_t *out_bytes)
+{
+    if (!db || !out_bytes)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    return encode_interest(db, db->iv_global[db->front], db->m_bits, out, out_cap, out_bytes, db->stream);
+}
+
+int pir_interest_delta_encoded(pir_db *db, uint64_t epoch, uint8_t *out, uint64_t out_cap, uint64_t *out_bytes)
+{
+    if (!db || !out_bytes)
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    if (epoch == 0 || epoch > db->epoch || epoch + db->window <= db->epoch)
+        return PIR_ERANGE;
+    HIP_TRY(hipSetDevice(db->device));
+    const uint32_t *slot = db->iv_ring + ((epoch - 1) % db->window) * db->iv_words;
+    return encode_interest(db, slot, db->m_bits, out, out_cap, out_bytes, db->stream);
 }
 
 int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void *hip_stream)
