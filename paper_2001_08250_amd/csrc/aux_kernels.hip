@@ -41,7 +41,7 @@ __global__ __launch_bounds__(WG) void fill_zero_kernel(uint32_t *__restrict__ p,
 
 // bit p lives in word p >> 5, bit p & 31 (little-endian: byte p >> 3, bit p & 7)
 // The device half of an epoch commit, one launch. Blocks below iv_blocks
-// each own 64 words of the interest vector: they OR the window's other
+// each own COMMIT_IV_WORDS words of the interest vector: they OR the window's other
 // slots, build the new epoch's delta from the positions that fall into their
 // words (the host sorted them by block), store the delta in its ring slot
 // (overwriting the epoch that leaves the window) and write the new global
@@ -59,16 +59,17 @@ __global__ __launch_bounds__(WG) void commit_kernel(const CommitArgs a)
             d[c] = s[c];
         return;
     }
-    __shared__ uint32_t part[WG / 64][64];
-    __shared__ uint32_t fresh[64];
-    const uint32_t lane = threadIdx.x & 63u, sl = threadIdx.x >> 6;
-    const uint64_t i = b * 64 + lane;
-    if (threadIdx.x < 64)
+    constexpr uint32_t W = COMMIT_IV_WORDS, SL = WG / COMMIT_IV_WORDS;
+    __shared__ uint32_t part[SL][W];
+    __shared__ uint32_t fresh[W];
+    const uint32_t lane = threadIdx.x % W, sl = threadIdx.x / W;
+    const uint64_t i = b * W + lane;
+    if (threadIdx.x < W)
         fresh[threadIdx.x] = 0u;
     uint32_t v = 0;
     if (i < a.words) {
-#pragma unroll 4
-        for (uint32_t r = sl; r < a.window; r += WG / 64)
+#pragma unroll 8
+        for (uint32_t r = sl; r < a.window; r += SL)
             if (r != a.slot)
                 v |= a.ring[(uint64_t)r * a.words + i];
     }
@@ -76,8 +77,8 @@ __global__ __launch_bounds__(WG) void commit_kernel(const CommitArgs a)
     __syncthreads();
     for (uint32_t j = a.pos_start[b] + threadIdx.x; j < a.pos_start[b + 1]; j += WG) {
         const uint32_t p = a.pos[j];
-        const uint64_t w = (uint64_t)(p >> 5) - b * 64;
-        if (w < 64)
+        const uint64_t w = (uint64_t)(p >> 5) - b * W;
+        if (w < W)
             atomicOr(&fresh[w], 1u << (p & 31u));
     }
     __syncthreads();
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(WG) void commit_kernel(const CommitArgs a)
         uint32_t o = fresh[lane];
         a.ring[(uint64_t)a.slot * a.words + i] = o;
 #pragma unroll
-        for (int k = 0; k < WG / 64; ++k)
+        for (uint32_t k = 0; k < SL; ++k)
             o |= part[k][lane];
         a.global[i] = o;
     }

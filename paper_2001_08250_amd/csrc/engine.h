@@ -34,6 +34,9 @@ struct ReadGeom {
     // serialized PIR: B x 8 key words (32-byte seeds) of the answers'
     // one-time masks, or none
     const uint32_t *keys = nullptr;
+    // Event that the read's last kernel records when it completes (through
+    // the dispatch itself, so no separate marker sits in the stream), or none.
+    hipEvent_t done = nullptr;
 };
 
 struct Plan {
@@ -58,9 +61,10 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus);
 bool plan_supported(const Plan &p);
 
 // Enqueue the read: kernels on `stream`; `partials` must hold
-// partial_bytes(g, p) bytes. When ev_begin / ev_end are given they are
-// recorded right before and right after the main read kernel (not the
-// staging or split-reduction kernels).
+// partial_bytes(g, p) bytes. When ev_begin / ev_end are given they take the
+// start and end times of the main read kernel's dispatch (not the staging or
+// split-reduction kernels); g.done, when given, is recorded once the read's
+// last kernel has completed.
 hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream,
                        hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
@@ -101,7 +105,7 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);       
 // into that reduction, or in place on the rows when there were no splits).
 hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream);
 hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                            uint64_t out_pitch, const uint32_t *keys, hipStream_t stream);
+                            uint64_t out_pitch, const uint32_t *keys, hipStream_t stream, hipEvent_t done = nullptr);
 
 // Leader combine (serialized PIR): out row r = XOR of the l input rows r.
 constexpr uint32_t COMBINE_MAX = 16;
@@ -117,6 +121,10 @@ hipError_t launch_xor_combine(const CombineArgs &a, hipStream_t stream);
 
 // Epoch commit, device half (one launch): staged rows into the back copy and
 // the interest-vector update (see commit_kernel).
+// Interest-vector words per commit block: a block's 256 threads are 16
+// slices of the window, so each thread ORs about window / 16 ring rows, all
+// loads in flight at once.
+constexpr uint32_t COMMIT_IV_WORDS = 16;
 struct CommitArgs {
     uint4 *back;               // back copy
     const uint4 *rows;         // nrows staged rows (stride16 uint4 each), mapped host memory
@@ -125,8 +133,8 @@ struct CommitArgs {
     uint32_t *global;          // global vector to write (the back copy's)
     uint32_t *ring;            // window x words deltas
     uint32_t window, slot;     // slot = this epoch's delta
-    uint64_t words, iv_blocks; // iv_blocks = ceil(words / 64)
-    const uint32_t *pos;       // positions sorted by 64-word block, mapped host memory
+    uint64_t words, iv_blocks; // iv_blocks = ceil(words / COMMIT_IV_WORDS)
+    const uint32_t *pos;       // positions sorted by block, mapped host memory
     const uint32_t *pos_start; // block b: pos[pos_start[b] .. pos_start[b + 1])
 };
 hipError_t launch_commit(const CommitArgs &a, hipStream_t stream);

@@ -8,6 +8,7 @@
 // written: fused into the split reduction (one thread per 16-byte column and
 // row), or in place when the read had no bucket splits. The leader
 // XORs the l servers' masked answers row by row.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -130,15 +131,15 @@ uint32_t blocks_for(uint64_t threads) { return (uint32_t)std::max<uint64_t>(1, (
 }  // namespace
 
 hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                            uint64_t out_pitch, const uint32_t *keys, hipStream_t stream)
+                            uint64_t out_pitch, const uint32_t *keys, hipStream_t stream, hipEvent_t done)
 {
     if (B == 0)
-        return hipSuccess;
+        return done ? hipEventRecord(done, stream) : hipSuccess;
     const uint32_t stride16 = (uint32_t)(stride / 16);
     const uint64_t threads = (uint64_t)B * stride16;
-    hipLaunchKernelGGL(mask_rows_kernel, dim3(blocks_for(threads)), dim3(WG), 0, stream,
-                       static_cast<const uint4 *>(partials), (uint64_t)B * stride16, splits, B, stride16,
-                       static_cast<uint4 *>(out), out_pitch / 16, keys);
+    hipExtLaunchKernelGGL(mask_rows_kernel, dim3(blocks_for(threads)), dim3(WG), 0, stream, nullptr, done, 0,
+                          static_cast<const uint4 *>(partials), (uint64_t)B * stride16, splits, B, stride16,
+                          static_cast<uint4 *>(out), out_pitch / 16, keys);
     return hipGetLastError();
 }
 

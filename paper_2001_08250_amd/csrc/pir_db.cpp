@@ -44,18 +44,37 @@ void destroy_stream_graph(Scratch &sc)
     sc.sig.clear();
 }
 
-int note_reader(pir_db *db, int b, hipStream_t s)
+// The event that tracks the readers of buffer b on stream s, created on first
+// use. It keeps timing enabled so that a kernel dispatch can record it.
+int reader_event(pir_db *db, int b, hipStream_t s, hipEvent_t *ev)
 {
     auto it = db->readers[b].find(s);
-    hipEvent_t ev;
     if (it == db->readers[b].end()) {
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreate(ev) != hipSuccess)
             return PIR_EDEVICE;
-        db->readers[b].emplace(s, ev);
+        db->readers[b].emplace(s, *ev);
     } else {
-        ev = it->second;
+        *ev = it->second;
     }
+    return PIR_OK;
+}
+
+int note_reader(pir_db *db, int b, hipStream_t s)
+{
+    hipEvent_t ev;
+    const int rc = reader_event(db, b, s, &ev);
+    if (rc != PIR_OK)
+        return rc;
     return hipEventRecord(ev, s) == hipSuccess ? PIR_OK : PIR_EDEVICE;
+}
+
+// Order `s` after the latest publication; no wait is enqueued when it has
+// already completed (the snapshot it wrote is then final for `s` as well).
+int wait_published(pir_db *db, hipStream_t s)
+{
+    if (hipEventQuery(db->published) == hipSuccess)
+        return PIR_OK;
+    return hipStreamWaitEvent(s, db->published, 0) == hipSuccess ? PIR_OK : PIR_EDEVICE;
 }
 
 ReadGeom read_geom(pir_db *db, const void *q, uint64_t qpitch, uint32_t B, void *out, uint64_t out_pitch)
@@ -456,10 +475,10 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
     // Interest vector: the open epoch's delta replaces the ring slot of the
     // epoch that leaves the window, and the new global vector (OR of the
     // window) goes with the back copy. The positions go to the kernel sorted
-    // by 64-word block (counting sort), in mapped host memory.
+    // by block of COMMIT_IV_WORDS words (counting sort), in mapped host memory.
     PIR_TRY(wait_upload(db, UP_POS));
     const uint64_t npos = db->pos_pending.size();
-    const uint64_t nb = (db->iv_words + 63) / 64;
+    const uint64_t nb = (db->iv_words + COMMIT_IV_WORDS - 1) / COMMIT_IV_WORDS;
     if (npos + nb + 1 > db->pos_host_cap) {
         if (db->pos_host)
             hipHostFree(db->pos_host);
@@ -473,12 +492,12 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
     uint32_t *start = db->pos_host, *sorted = db->pos_host + nb + 1;
     memset(start, 0, (nb + 1) * 4);
     for (uint32_t p : db->pos_pending)
-        ++start[(p >> 5) / 64 + 1];
+        ++start[(p >> 5) / COMMIT_IV_WORDS + 1];
     for (uint64_t b = 0; b < nb; ++b)
         start[b + 1] += start[b];
     db->pos_cursor.assign(start, start + nb);
     for (uint32_t p : db->pos_pending)
-        sorted[db->pos_cursor[(p >> 5) / 64]++] = p;
+        sorted[db->pos_cursor[(p >> 5) / COMMIT_IV_WORDS]++] = p;
 
     // The back copy's vector may still be read by async readers of the
     // buffer it belonged to before the last swap.
@@ -618,7 +637,7 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     HIP_TRY(hipSetDevice(db->device));
-    HIP_TRY(hipStreamWaitEvent(s, db->published, 0));
+    PIR_TRY(wait_published(db, s));
     Scratch &sc = scratch_for(db, s);
     const void *q = d_req;
     uint64_t qp = req_pitch;
@@ -643,13 +662,17 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     g.keys = static_cast<const uint32_t *>(d_keys);
     Plan p = choose_plan(db, B);
     PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
-    hipEvent_t eb, ee;
+    hipEvent_t eb, ee, done;
     PIR_TRY(profile_slot(db, &eb, &ee));
+    PIR_TRY(reader_event(db, db->front, s, &done));
+    if (direct)
+        g.done = done;  // the read's last kernel marks the end of its use of the snapshot
     HIP_TRY(launch_read(g, p, sc.part, s, eb, ee));
-    if (!direct)
-        HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,
-                                 hipMemcpyDeviceToDevice, s));
-    return note_reader(db, db->front, s);
+    if (direct)
+        return PIR_OK;
+    HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,
+                             hipMemcpyDeviceToDevice, s));
+    return hipEventRecord(done, s) == hipSuccess ? PIR_OK : PIR_EDEVICE;
 }
 
 int pir_read_batch(pir_db *db, const uint8_t *req_bits, uint32_t B, uint8_t *resp)
@@ -826,7 +849,7 @@ int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void 
     if (out_bytes < bytes)
         return PIR_EINVAL;
     HIP_TRY(hipSetDevice(db->device));
-    HIP_TRY(hipStreamWaitEvent(s, db->published, 0));
+    PIR_TRY(wait_published(db, s));
     HIP_TRY(hipMemcpyAsync(d_out, db->iv_global[db->front], bytes, hipMemcpyDeviceToDevice, s));
     return note_reader(db, db->front, s);
 }

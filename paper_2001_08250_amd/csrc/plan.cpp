@@ -115,13 +115,13 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 }
 
 hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream);
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
 
 hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream)
 {
     if (g.keys)
-        return launch_mask_rows(partials, splits, g.B, g.stride, g.out, g.out_pitch, g.keys, stream);
-    return launch_xor_splits(partials, splits, g.B, g.stride, g.out, g.out_pitch, stream);
+        return launch_mask_rows(partials, splits, g.B, g.stride, g.out, g.out_pitch, g.keys, stream, g.done);
+    return launch_xor_splits(partials, splits, g.B, g.stride, g.out, g.out_pitch, stream, g.done);
 }
 
 hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t ev_begin,
@@ -137,8 +137,12 @@ hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStre
     else
         e = launch_tile_read(g, p, partials, stream, ev_begin, ev_end);
     // without splits the kernel wrote the plain answers: mask them in place
-    if (e == hipSuccess && g.keys && p.splits <= 1)
-        e = launch_mask_rows(nullptr, 0, g.B, g.stride, g.out, g.out_pitch, g.keys, stream);
+    if (e == hipSuccess && p.splits <= 1) {
+        if (g.keys)
+            e = launch_mask_rows(nullptr, 0, g.B, g.stride, g.out, g.out_pitch, g.keys, stream, g.done);
+        else if (g.done)
+            e = hipEventRecord(g.done, stream);
+    }
     return e;
 }
 

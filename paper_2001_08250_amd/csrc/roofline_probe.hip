@@ -20,8 +20,12 @@ namespace {
 constexpr int N = 16384;  // dwords = 64 KiB
 constexpr int ITERS = 2000;
 
-// MODE 0: reads of W dwords per lane; MODE 1: 16-byte writes; MODE 2: four
-// 16-byte reads per 16-byte write (a table lookup phase with a build share).
+// MODE 0: reads of W dwords per lane; MODE 1: writes of W dwords per lane;
+// MODE 2: four 16-byte reads per 16-byte write; MODE 3: the paired lookup of
+// the Four-Russians kernels (per two 16-byte reads at wave-uniform, loop
+// varying row offsets: two address adds and four three-input XORs into the
+// accumulator); MODE 4: MODE 3 with two of every sixteen accesses turned into
+// 16-byte writes (the lookup-to-build byte ratio of paired 32-entry tables).
 template <int MODE, int W>
 __global__ __launch_bounds__(256) void lds_probe(uint32_t *out, int iters)
 {
@@ -29,13 +33,29 @@ __global__ __launch_bounds__(256) void lds_probe(uint32_t *out, int iters)
     for (int i = threadIdx.x; i < N; i += 256)
         s[i] = i * 2654435761u;
     __syncthreads();
-    uint4 acc = make_uint4(threadIdx.x, 1u, 2u, 3u);
+    uint4 acc = make_uint4(threadIdx.x, 1u, 2u, 3u), pa = acc;
     const int base = threadIdx.x * W;  // < 1024 dwords
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int o = base + k * 256 * W;  // <= 1020 + 15 * 1024 = 16380, +3 < N
-            if constexpr (MODE == 0) {
+            // row offset in [0, 15] * 1024 dwords, the same for the whole wave
+            const int ov = base + (((it * 5 + k) & 15) << 10);
+            if constexpr (MODE >= 3) {
+                static_assert(W == 4, "paired lookups are 16 bytes per lane");
+                if (MODE == 4 && k >= 14) {
+                    acc.x += 1u;
+                    *reinterpret_cast<uint4 *>(&s[ov]) = acc;
+                } else if (k % 2 == 0) {
+                    pa = *reinterpret_cast<const uint4 *>(&s[ov]);
+                } else {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(&s[ov]);
+                    acc.x = __builtin_amdgcn_bitop3_b32(acc.x, pa.x, v.x, 0x96);
+                    acc.y = __builtin_amdgcn_bitop3_b32(acc.y, pa.y, v.y, 0x96);
+                    acc.z = __builtin_amdgcn_bitop3_b32(acc.z, pa.z, v.z, 0x96);
+                    acc.w = __builtin_amdgcn_bitop3_b32(acc.w, pa.w, v.w, 0x96);
+                }
+            } else if constexpr (MODE == 0) {
                 if constexpr (W == 1) {
                     acc.x ^= s[o];
                 } else if constexpr (W == 2) {
@@ -51,7 +71,12 @@ __global__ __launch_bounds__(256) void lds_probe(uint32_t *out, int iters)
                 }
             } else if constexpr (MODE == 1) {
                 acc.x += 1u;
-                *reinterpret_cast<uint4 *>(&s[o]) = acc;
+                if constexpr (W == 1)
+                    s[o] = acc.x;
+                else if constexpr (W == 2)
+                    *reinterpret_cast<uint2 *>(&s[o]) = make_uint2(acc.x, acc.y);
+                else
+                    *reinterpret_cast<uint4 *>(&s[o]) = acc;
             } else {
                 if (k % 5 == 4) {
                     *reinterpret_cast<uint4 *>(&s[o]) = acc;
@@ -183,8 +208,12 @@ int main()
     rc |= run<0, 1>("ds_read_b32 (4 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 2>("ds_read_b64 (8 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 4>("ds_read_b128 (16 B per lane)", d, p.multiProcessorCount);
+    rc |= run<1, 1>("ds_write_b32 (4 B per lane)", d, p.multiProcessorCount);
+    rc |= run<1, 2>("ds_write_b64 (8 B per lane)", d, p.multiProcessorCount);
     rc |= run<1, 4>("ds_write_b128 (16 B per lane)", d, p.multiProcessorCount);
     rc |= run<2, 4>("4 ds_read_b128 : 1 ds_write_b128", d, p.multiProcessorCount);
+    rc |= run<3, 4>("paired lookups (2 adds + 4 xor3 / 2 reads)", d, p.multiProcessorCount);
+    rc |= run<4, 4>("paired lookups + 1/8 ds_write_b128", d, p.multiProcessorCount);
     (void)hipFree(d);
     return rc;
 }

@@ -169,7 +169,7 @@ extern "C" int pir_read_stream_async(pir_db *db, const void *d_req, uint64_t req
     }
     sig.insert(sig.end(), idx.begin(), idx.end());
 
-    if (hipStreamWaitEvent(s, db->published, 0) != hipSuccess)
+    if (wait_published(db, s) != PIR_OK)
         return PIR_EDEVICE;
     if (sc.exec && sc.sig == sig) {
         if (hipGraphLaunch(sc.exec, s) != hipSuccess)

@@ -24,6 +24,7 @@
 //    accumulation one v_xor.
 //  * Splits over bucket ranges and the XCD-aware task order are as in the
 //    tiled kernels; partial answers are reduced by the same second pass.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +34,7 @@
 namespace talek {
 
 hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream);
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
 
 namespace {
 
@@ -272,12 +273,8 @@ hipError_t launch_m4r_read(const ReadGeom &g, const Plan &p, void *partials, hip
     }
     const uint64_t tasks = (uint64_t)a.n_rt * a.n_slices * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
-    if (eb && hipEventRecord(eb, stream) != hipSuccess)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, a);
+    hipExtLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, eb, ee, 0, a);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && ee)
-        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_split_reduce(partials, p.splits, g, stream);

@@ -14,6 +14,7 @@
 // pre-scaled, wave-uniform offset), one ds_read_b128 and four v_xor_b32 for
 // 24 (bucket, dword) terms. The table costs 63 x 4 XORs and 64 ds_write_b128
 // per group, split over the workgroup's waves and shared by all its requests.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,7 +24,7 @@
 namespace talek {
 
 hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream);
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
 
 namespace {
 
@@ -698,12 +699,8 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     }
     const uint64_t tasks = (uint64_t)a.n_rt * a.slices * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
-    if (eb && hipEventRecord(eb, stream) != hipSuccess)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, a);
+    hipExtLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, eb, ee, 0, a);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && ee)
-        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_split_reduce(partials, p.splits, g, stream);

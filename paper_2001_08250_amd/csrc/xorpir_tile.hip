@@ -25,6 +25,7 @@
 //    with request tiles fastest. The request tiles that share a (split,
 //    column group) slice of D then run together on one XCD and reuse it from
 //    that XCD's L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -246,15 +247,16 @@ TileFn tile_fn(const Plan &p)
 bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
 
 hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream)
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done)
 {
     const uint32_t stride16 = (uint32_t)(stride / 16);
     const uint64_t count = (uint64_t)B * stride16;
     if (count == 0)
-        return hipSuccess;
+        return done ? hipEventRecord(done, stream) : hipSuccess;
     const uint32_t rgrid = (uint32_t)((count + WG - 1) / WG);
-    hipLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream, static_cast<const uint4 *>(partials),
-                       count, splits, count, stride16, static_cast<uint4 *>(out), out_pitch / 16);
+    hipExtLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream, nullptr, done, 0,
+                          static_cast<const uint4 *>(partials), count, splits, count, stride16,
+                          static_cast<uint4 *>(out), out_pitch / 16);
     return hipGetLastError();
 }
 
@@ -290,12 +292,8 @@ hipError_t launch_tile_read(const ReadGeom &g, const Plan &p, void *partials, hi
     const uint64_t tasks = (uint64_t)a.n_rt * a.n_cg * a.splits;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
     const uint32_t grid = a.tasks_per_xcd * 8;
-    if (eb && hipEventRecord(eb, stream) != hipSuccess)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(WG), 0, stream, a);
+    hipExtLaunchKernelGGL(fn, dim3(grid), dim3(WG), 0, stream, eb, ee, 0, a);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && ee)
-        e = hipEventRecord(ee, stream);
     if (e != hipSuccess || p.splits <= 1)
         return e;
     return launch_split_reduce(partials, p.splits, g, stream);
