@@ -31,6 +31,31 @@ from synth import configs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit VALU lane-ops per second: 39.3 T
+# LDS rates measured by the roofline probe (bytes per clock and CU, 16-byte
+# accesses, no bank conflicts), at 256 CUs and 2.4 GHz
+LDS_READ_BPC, LDS_WRITE_BPC = 204.9, 75.4
+
+
+def lds_floor(plan, n: int, B: int, bucket_bytes: int):
+    """Algorithmic LDS traffic of a Four-Russians (wide) read launch and the
+    time it takes at the measured LDS rates: every request looks up one 1 KiB
+    table row per table (a 6-bucket table, or two 5-bucket tables per step
+    with paired tables), and every workgroup writes its step's tables once."""
+    if plan.kind != 4:
+        return None
+    pairs = bool(plan.flags & (1 << 13))
+    per_step = 10 if pairs else 6
+    tables, entries = (2, 32) if pairs else (1, 64)
+    steps = -(-n // per_step)
+    slices = -(-bucket_bytes // 1024)
+    R = plan.tile * plan.unroll
+    tiles = -(-B // R)
+    rows = -(-B // plan.tile) * plan.tile              # requests of the active waves
+    rd = slices * steps * rows * tables * 1024
+    wr = slices * tiles * steps * tables * entries * 1024
+    clk = 256 * 2.4e9
+    floor_s = rd / (LDS_READ_BPC * clk) + wr / (LDS_WRITE_BPC * clk)
+    return {"read_bytes": rd, "write_bytes": wr, "floor_ms": round(1e3 * floor_s, 4)}
 INTEREST_K = 6
 IV_BITS = 1 << 17        # global interest vector: 16 KiB (the paper's ~14 KB at 1M messages)
 IV_WINDOW = 100          # deltas kept: the paper's TTL of 100 write intervals
@@ -282,6 +307,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--read-streams", type=int, default=1,
+                    help="read streams that consecutive batches take in turn (1 = every batch on one stream)")
     ap.add_argument("--masked", action="store_true",
                     help="serialized PIR: every answer XORed with a ChaCha20 one-time mask from a per-request seed")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
@@ -353,15 +380,20 @@ def main():
     q = torch.from_numpy(req).to(dev)
     seeds = synth.uniform_bytes(w.req_seed + 99, B * 32).reshape(B, 32) if args.masked else None
     seeds_dev = torch.from_numpy(seeds).to(dev) if args.masked else None
-    out = torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev)
+    # Consecutive batches are independent; with R > 1 they go out on R read
+    # streams in turn (default priority), so that one batch's split reduction
+    # and the next batch's offset staging can overlap the neighbouring main
+    # kernel. The main kernel's event-timed duration then includes its wait
+    # for compute units, so the default is one stream.
+    R = max(1, args.read_streams)
+    read_streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev) for _ in range(R - 1)]
+    outs = [torch.empty((B, w.bucket_bytes), dtype=torch.uint8, device=dev) for _ in range(R)]
     iv = torch.empty((IV_BITS // 8,), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
     # The interest-vector fetch depends only on the published epoch, not on
     # the read, so it goes out on a second stream (default priority) beside it.
     iv_stream = torch.cuda.Stream(device=dev)
     iv_sh = int(iv_stream.cuda_stream)
     L = pir.lib()
-    sh = int(stream.cuda_stream)
 
     # host seconds per part of the step, summed over the timed steps
     host_s = {"insert": 0.0, "stage": 0.0, "interest_add": 0.0, "commit": 0.0, "read_call": 0.0}
@@ -389,10 +421,11 @@ def main():
         if full:
             do_writes(k)
         t = time.perf_counter()
+        rs, out = read_streams[k % R], outs[k % R]
         if seeds_dev is not None:
-            db.read_masked_async(q, seeds_dev, out)
+            db.read_masked_async(q, seeds_dev, out, stream=rs)
         else:
-            db.read_async(q, out)
+            db.read_async(q, out, stream=rs)
         host_s["read_call"] += time.perf_counter() - t
         if full:
             rc = L.pir_interest_vector_async(db.h, iv.data_ptr(), iv.numel(), iv_sh)
@@ -434,7 +467,7 @@ def main():
                  "global_encode_ms": round(1e3 * t_enc, 3)}
     assert kern.size == min(K, pir.PROFILE_MAX)
     kern_ms = float(np.mean(kern))
-    got = out.cpu().numpy()
+    got = outs[(W + K - 1) % R].cpu().numpy()   # the last step's answers
     got_iv = iv.cpu().numpy()
 
     ms_per_step = 1000.0 * wall / K
@@ -454,6 +487,10 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None}
     roof["traffic"] = measured_traffic(w.name, plan)
+    lds = lds_floor(plan, w.n, B, w.bucket_bytes)
+    if lds:
+        lds["frac"] = round(lds["floor_ms"] / kern_ms, 4)   # of the LDS-bound floor
+        roof["lds"] = lds
     roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
                 plain_xor_tops=round(alu_achieved, 3), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
 
@@ -507,7 +544,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "B": B,
                    "step": ("writes+commit+read+interest" if full else "read") + (" (masked)" if args.masked else ""),
-                   "writes_per_step": nw,
+                   "writes_per_step": nw, "read_streams": R,
                    "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll,
                             "flags": plan.flags},
                    "parallelism": "single-gpu"},

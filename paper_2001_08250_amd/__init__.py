@@ -88,7 +88,7 @@ SIGNATURES = {
     "pir_db_create": (ctypes.c_int, [_u64, _u32, _u32, ctypes.POINTER(_vp)]),
     "pir_db_destroy": (None, [_vp]),
     "pir_db_shape": (ctypes.c_int, [_vp, _u64p, _u32p, _u32p, _u64p]),
-    "pir_db_write_bucket": (ctypes.c_int, [_vp, _u64, _u8p]),
+    "pir_db_write_bucket": (ctypes.c_int, [_vp, _u64, _vp]),
     "pir_db_write_range": (ctypes.c_int, [_vp, _u64, _u64, _u8p]),
     "pir_epoch_commit": (ctypes.c_int, [_vp, _u64p]),
     "pir_epoch": (_u64, [_vp]),
@@ -107,7 +107,7 @@ SIGNATURES = {
     "pir_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_uint32,
                                            ctypes.POINTER(ctypes.c_uint32)]),
     "pir_interest_config": (ctypes.c_int, [_vp, _u64, _u32]),
-    "pir_interest_add": (ctypes.c_int, [_vp, _u32p, _u32]),
+    "pir_interest_add": (ctypes.c_int, [_vp, _vp, _u32]),
     "pir_interest_vector": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_interest_vector_async": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "pir_interest_vector_encoded": (ctypes.c_int, [_vp, _u8p, _u64, _u64p]),
@@ -116,7 +116,7 @@ SIGNATURES = {
     "pir_cuckoo_create_detached": (ctypes.c_int, [_u64, _u32, _u32, _u64, _u64, _u32, ctypes.POINTER(_vp)]),
     "pir_cuckoo_destroy": (None, [_vp]),
     "pir_cuckoo_insert": (ctypes.c_int, [_vp, _u64, _u64, _u64, _u8p, _u64p]),
-    "pir_cuckoo_insert_many": (ctypes.c_int, [_vp, _u64, _u64p, _u64p, _u64p, _u8p, _i32p, _u64p]),
+    "pir_cuckoo_insert_many": (ctypes.c_int, [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pir_cuckoo_stage": (ctypes.c_int, [_vp, _u64p]),
     "pir_cuckoo_table": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_cuckoo_slots": (ctypes.c_int, [_vp, _u64p, _u8p]),
@@ -173,6 +173,12 @@ def _check(rc: int, what: str):
 
 def _ptr(a: np.ndarray, ct=ctypes.c_uint8):
     return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _addr(a: np.ndarray) -> int:
+    """Address of a contiguous array's data, for void-pointer arguments (a few
+    times cheaper than building a typed ctypes pointer on every call)."""
+    return a.__array_interface__["data"][0]
 
 
 def __getattr__(name):  # raw C entry points under their own names
@@ -233,7 +239,7 @@ class PirDB:
         data = np.ascontiguousarray(data, dtype=np.uint8)
         if data.size != self.bucket_bytes:
             raise ValueError("bucket data has the wrong size")
-        _check(self._L.pir_db_write_bucket(self.h, bucket, _ptr(data)), "pir_db_write_bucket")
+        _check(self._L.pir_db_write_bucket(self.h, bucket, _addr(data)), "pir_db_write_bucket")
 
     def write_range(self, first: int, data: np.ndarray):
         data = np.ascontiguousarray(data, dtype=np.uint8)
@@ -348,7 +354,7 @@ class PirDB:
 
     def interest_add(self, pos):
         pos = np.ascontiguousarray(pos, dtype=np.uint32).reshape(-1)
-        _check(self._L.pir_interest_add(self.h, _ptr(pos, ctypes.c_uint32), pos.size), "pir_interest_add")
+        _check(self._L.pir_interest_add(self.h, _addr(pos), pos.size), "pir_interest_add")
 
     def interest_encoded(self, epoch: int | None = None) -> bytes:
         """Compressed stream of the global vector (epoch None) or of a published
@@ -474,10 +480,8 @@ class Cuckoo:
         payloads = np.ascontiguousarray(payloads, dtype=np.uint8)
         status = np.zeros(ids.size, dtype=np.int32)
         dropped = np.zeros(ids.size, dtype=np.uint64)
-        _check(self._L.pir_cuckoo_insert_many(self.h, ids.size, _ptr(ids, ctypes.c_uint64), _ptr(b1, ctypes.c_uint64),
-                                              _ptr(b2, ctypes.c_uint64), _ptr(payloads),
-                                              _ptr(status, ctypes.c_int32), _ptr(dropped, ctypes.c_uint64)),
-               "pir_cuckoo_insert_many")
+        _check(self._L.pir_cuckoo_insert_many(self.h, ids.size, _addr(ids), _addr(b1), _addr(b2), _addr(payloads),
+                                              _addr(status), _addr(dropped)), "pir_cuckoo_insert_many")
         return status, dropped
 
     def stage(self) -> int:

@@ -379,3 +379,50 @@ def test_kernel_timing_records_each_read():
         assert db.profile_collect().size == 0
         torch.cuda.synchronize()
         assert_rows_equal(out.cpu().numpy(), want, "async read")
+
+
+@pytest.mark.parametrize("forced", [None, (pir.KERNEL_M4R_WIDE, 8, 1, 8, pir.PLAN_PAIRS),
+                                    (pir.KERNEL_SKIP, 16, 1, 4, 0)])
+def test_async_reads_on_two_streams_see_their_epoch(forced):
+    """Reads queued on two streams between commits, with no host wait, each
+    answer from the snapshot published before they were issued: the commits'
+    mirror copies wait for the reads still using the other copy (the read's
+    last kernel marks its end), and the interest fetch beside each read gets
+    the same epoch's vector. Automatic plan (split reduction last) and plans
+    without splits (main kernel last)."""
+    import torch
+    n, d, z, B, m, window, epochs = 8192, 2, 1024, 64, 1 << 12, 3, 6
+    rng = np.random.default_rng(95)
+    D = synth.uniform_db(93, n, d * z)
+    req = synth.bernoulli_requests(94, B, n)
+    dev = torch.device("cuda:0")
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream(device=dev)]
+    snaps, vecs = [], []
+    with pir.PirDB(n, d, z) as db:
+        db.interest_config(m, window)
+        db.write_range(0, D)
+        db.commit()
+        if forced:
+            db.set_plan(*forced)
+        q = torch.from_numpy(req).to(dev)
+        outs = [torch.zeros((B, d * z), dtype=torch.uint8, device=dev) for _ in range(epochs)]
+        ivs = [torch.zeros((m // 8,), dtype=torch.uint8, device=dev) for _ in range(epochs)]
+        pos_by_epoch = [np.zeros(0, np.uint32)]    # commit 0 = the load
+        for e in range(epochs):
+            for b in rng.choice(n, size=40, replace=False):
+                D[b] = rng.integers(0, 256, d * z, dtype=np.uint8)
+                db.write_bucket(int(b), D[b])
+            pos = rng.integers(0, m, 30, dtype=np.uint32)
+            db.interest_add(pos)
+            db.commit()
+            pos_by_epoch.append(pos)
+            snaps.append(D.copy())
+            vecs.append(oracle.interest_window(m, pos_by_epoch, len(pos_by_epoch) - 1, window))
+            s = streams[e % 2]
+            db.read_async(q, outs[e], stream=s)
+            rc = pir.lib().pir_interest_vector_async(db.h, ivs[e].data_ptr(), ivs[e].numel(), int(s.cuda_stream))
+            assert rc == 0
+        torch.cuda.synchronize()
+        for e in range(epochs):
+            assert_rows_equal(outs[e].cpu().numpy(), oracle.pir_read(snaps[e], req), f"epoch {e + 1}")
+            assert np.array_equal(ivs[e].cpu().numpy(), vecs[e]), f"interest vector of epoch {e + 1}"
