@@ -309,6 +309,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--read-streams", type=int, default=1,
                     help="read streams that consecutive batches take in turn (1 = every batch on one stream)")
+    ap.add_argument("--prep", type=int, default=0, choices=[0, 1, 2],
+                    help="answer through L levels of Strassen leaves formed at commit (large batches)")
     ap.add_argument("--masked", action="store_true",
                     help="serialized PIR: every answer XORed with a ChaCha20 one-time mask from a per-request seed")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
@@ -368,6 +370,11 @@ def main():
         ipos = synth.interest_positions(w.req_seed + 7, total_w, INTEREST_K, IV_BITS)
 
     req = synth.bernoulli_requests(w.req_seed, B, w.n)
+    if args.prep:
+        t = time.perf_counter()
+        db.preprocess(args.prep, 1)
+        torch.cuda.synchronize()
+        log(f"[bench] preprocessed ({args.prep} Strassen levels) in {time.perf_counter() - t:.2f}s")
     if args.kind:
         db.set_plan(args.kind, args.tile, args.splits, args.unroll, args.flags)
     if args.tune:
@@ -487,7 +494,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None}
     roof["traffic"] = measured_traffic(w.name, plan)
-    lds = lds_floor(plan, w.n, B, w.bucket_bytes)
+    lds = None if args.prep else lds_floor(plan, w.n, B, w.bucket_bytes)
     if lds:
         lds["frac"] = round(lds["floor_ms"] / kern_ms, 4)   # of the LDS-bound floor
         roof["lds"] = lds
@@ -513,7 +520,8 @@ def main():
                 D = D0.copy()
                 for i in range(total_w):
                     D[int(wr[1][i])] = wr[3][i]
-        rows = np.arange(min(args.cpu_rows, B))
+        # sampled rows spread over the batch (every block of a preprocessed read)
+        rows = np.unique(np.linspace(0, B - 1, min(args.cpu_rows, B)).round().astype(np.int64))
         t1 = time.perf_counter()
         want = (oracle.pir_read_masked(D, req[rows], seeds[rows], threads=threads) if args.masked
                 else oracle.pir_read(D, req[rows], threads=threads))
@@ -544,7 +552,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "B": B,
                    "step": ("writes+commit+read+interest" if full else "read") + (" (masked)" if args.masked else ""),
-                   "writes_per_step": nw, "read_streams": R,
+                   "writes_per_step": nw, "read_streams": R, "strassen_levels": args.prep,
                    "plan": {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll,
                             "flags": plan.flags},
                    "parallelism": "single-gpu"},

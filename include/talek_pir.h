@@ -416,6 +416,35 @@ typedef struct pir_serve_result {
 int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
                   const pir_serve_trace *trace, pir_serve_result *res);
 
+/* ---- Preprocessed reads for large batches ----------------------------------
+ *
+ * A batch's answers are the GF(2) product of its request bits (B x n) with
+ * the snapshot (n x d*msg_bytes); the server side of the method (section
+ * "Talek Server", the XOR of the selected buckets) fixes this product, not
+ * how it is computed. With preprocessing on, the library applies L levels
+ * (1 or 2) of Strassen's block recursion, whose seven block products per
+ * level need only XORs over GF(2): the database side of every one of the
+ * 7^L leaf products (an XOR of up to 2^L blocks of the snapshot) is formed
+ * once per epoch commit, and a read forms the request blocks, answers the
+ * 7^L leaf products with the usual kernels and XORs them into the answers.
+ * The answers are exactly those of the plain definition; a large read does
+ * 7^L / 8^L of the plain product's work, at the price of 7^L / 4^L times the
+ * snapshot in device memory (1.75 at L = 1, 3.06 at L = 2) and one pass over
+ * it in every commit that changes the snapshot (the delay before writes
+ * become readable grows by that pass).
+ *
+ *   levels:    0 (off, frees the leaves), 1 or 2.
+ *   min_batch: reads of B >= min_batch rows take the preprocessed path
+ *              (pir_read_batch*, masked or not); 0 selects 256 << levels,
+ *              where each leaf product still has a full Four-Russians tile.
+ *              The uneven-batch stream and the serving loop keep the plain
+ *              path.
+ * Errors: PIR_EINVAL for levels > 2 or d * msg_bytes not a multiple of
+ * 16 << levels; PIR_ENOMEM when the leaves do not fit. The leaves are built
+ * from the published snapshot at once (stream-ordered; reads wait for them).
+ */
+int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch);
+
 #ifdef __cplusplus
 }
 #endif

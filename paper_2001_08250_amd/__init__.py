@@ -108,6 +108,7 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_uint32)]),
     "pir_interest_config": (ctypes.c_int, [_vp, _u64, _u32]),
     "pir_interest_add": (ctypes.c_int, [_vp, _vp, _u32]),
+    "pir_preprocess": (ctypes.c_int, [_vp, _u32, _u32]),
     "pir_interest_vector": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_interest_vector_async": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "pir_interest_vector_encoded": (ctypes.c_int, [_vp, _u8p, _u64, _u64p]),
@@ -351,6 +352,11 @@ class PirDB:
     def interest_config(self, m_bits: int = IV_DEFAULT_BITS, window: int = IV_DEFAULT_WINDOW):
         _check(self._L.pir_interest_config(self.h, m_bits, window), "pir_interest_config")
         self.m_bits = m_bits
+
+    def preprocess(self, levels: int, min_batch: int = 0):
+        """Strassen-preprocessed reads for batches of >= min_batch rows (0: 256 << levels);
+        levels 0 turns them off."""
+        _check(self._L.pir_preprocess(self.h, levels, min_batch), "pir_preprocess")
 
     def interest_add(self, pos):
         pos = np.ascontiguousarray(pos, dtype=np.uint32).reshape(-1)

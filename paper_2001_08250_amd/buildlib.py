@@ -27,6 +27,7 @@ SOURCES = [
     "serve.cpp",
     "mask.hip",
     "iv_codec.hip",
+    "strassen.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value", f"-I{os.path.join(ROOT, 'include')}"]

@@ -27,6 +27,10 @@ struct Scratch {
     uint64_t aux_cap = 0;
     void *keys = nullptr;     // mask seeds of a synchronous masked read
     uint64_t keys_cap = 0;
+    void *leaf_q = nullptr;   // preprocessed reads: leaf requests and products
+    uint64_t leaf_q_cap = 0;
+    void *leaf_out = nullptr;
+    uint64_t leaf_out_cap = 0;
     hipGraphExec_t exec = nullptr;  // captured stream read
     std::vector<uint64_t> sig;      // what the captured graph bakes in
 };
@@ -61,8 +65,9 @@ struct pir_db {
     bool have_back = false;
     uint64_t epoch = 0;
     hipEvent_t published = nullptr;  // end of the last commit's device work
-    // events recorded after async reads, per buffer and per stream
-    std::map<hipStream_t, hipEvent_t> readers[2];
+    // events recorded after async reads, per buffer and per stream; index 2
+    // tracks the readers of the preprocessed leaf databases
+    std::map<hipStream_t, hipEvent_t> readers[3];
 
     // staged bucket writes (mapped pinned host rows, `stride` bytes each;
     // the commit kernels read them in place through the *_map pointers)
@@ -108,6 +113,15 @@ struct pir_db {
     void *codec = nullptr, *codec2 = nullptr, *codec3 = nullptr;
     uint64_t codec_cap = 0, codec2_cap = 0, codec3_cap = 0;
     uint64_t mirror_idx_cap = 0;
+    // preprocessed reads: the Strassen leaf databases of the published
+    // snapshot, rebuilt by every commit that changes it
+    uint32_t prep_levels = 0;       // 0 = off
+    uint32_t prep_min_batch = 0;    // reads with B >= this take the leaves
+    talek::PrepTables prep_t{};
+    uint8_t *prep = nullptr;        // prep_t.leaves x prep_leaf_bytes
+    uint64_t prep_leaf_bytes = 0;
+    uint64_t prep_Nq = 0;           // bucket rows per block (multiple of 32)
+    uint32_t prep_Cq = 0;           // bytes per bucket block
 };
 
 namespace talek {

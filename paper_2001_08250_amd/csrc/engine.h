@@ -141,4 +141,32 @@ hipError_t launch_commit(const CommitArgs &a, hipStream_t stream);
 
 
 
+// --- preprocessed reads (Strassen leaves over the Four-Russians kernels) --
+constexpr uint32_t PREP_MAX_LEVELS = 2;
+constexpr uint32_t PREP_MAX_LEAVES = 49;  // 7^2
+constexpr uint32_t PREP_MAX_BLOCKS = 16;  // C blocks at two levels (4 x 4)
+// Leaf tables of an L-level recursion: leaf i sums the A blocks a[i][..]
+// and the D blocks d[i][..] ((row << 4) | col in the 2^L grid); C block b
+// (row * grid + col) is the XOR of the leaves o_leaf[b][..].
+struct PrepTables {
+    uint32_t leaves, grid;
+    uint8_t a_cnt[PREP_MAX_LEAVES], d_cnt[PREP_MAX_LEAVES];
+    uint8_t a[PREP_MAX_LEAVES][4], d[PREP_MAX_LEAVES][4];
+    uint8_t o_cnt[PREP_MAX_BLOCKS];
+    uint8_t o_leaf[PREP_MAX_BLOCKS][16];
+};
+bool prep_tables(uint32_t levels, PrepTables *t);
+// Leaf databases: leaf i (leaf_bytes apart, rows Cq bytes) = XOR of its D
+// blocks, rows Nq per block (rows >= n of D read as zero).
+hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, uint64_t n, uint64_t Nq, uint32_t Cq,
+                         void *out, uint64_t leaf_bytes, hipStream_t stream);
+// Leaf requests: leaf i (leaf_bytes apart, rows out_pitch bytes, Bq rows of
+// Wq words) = XOR of its A blocks of the B request rows (bits >= n zero).
+hipError_t launch_prep_q(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t Bq,
+                         uint64_t Wq, void *out, uint64_t out_pitch, uint64_t leaf_bytes, hipStream_t stream);
+// Answers: row r < B of `out` = the XOR of the leaf products (Bq x Cq bytes
+// each, leaf_bytes apart) that reach each of its blocks; records `done`.
+hipError_t launch_prep_out(const PrepTables &t, const void *leaves, uint64_t leaf_bytes, uint32_t B, uint32_t Bq,
+                           uint32_t Cq, void *out, uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
+
 }  // namespace talek

@@ -272,13 +272,17 @@ void free_db(pir_db *db)
         hipFree(kv.second.part);
         hipFree(kv.second.aux);
         hipFree(kv.second.keys);
+        hipFree(kv.second.leaf_q);
+        hipFree(kv.second.leaf_out);
     }
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 3; ++b)
         for (auto &kv : db->readers[b])
             hipEventDestroy(kv.second);
+    for (int b = 0; b < 2; ++b) {
         hipFree(db->buf[b]);
         hipFree(db->iv_global[b]);
     }
+    hipFree(db->prep);
     hipFree(db->iv_ring);
     if (db->stage_host)
         hipHostFree(db->stage_host);
@@ -458,6 +462,16 @@ int pir_db_write_range(pir_db *db, uint64_t first, uint64_t count, const uint8_t
     return PIR_OK;
 }
 
+// Leaf databases of preprocessed reads from snapshot buffer b, on the
+// handle's stream once the reads still using the old leaves are done.
+static int build_prep(pir_db *db, int b)
+{
+    PIR_TRY(wait_readers(db, 2, db->stream));
+    HIP_TRY(launch_prep_d(db->prep_t, db->buf[b], db->stride, db->n, db->prep_Nq, db->prep_Cq, db->prep,
+                          db->prep_leaf_bytes, db->stream));
+    return PIR_OK;
+}
+
 int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 {
     if (!db)
@@ -538,7 +552,10 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
             *epoch_out = db->epoch;
         return PIR_OK;
     }
-    // publish: swap the copies
+    // publish: swap the copies (the leaf databases of preprocessed reads
+    // are rebuilt from the new snapshot first)
+    if (db->prep)
+        PIR_TRY(build_prep(db, back));
     HIP_TRY(hipEventRecord(db->published, db->stream));
     const int old_front = db->front;
     db->front = back;
@@ -579,6 +596,50 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 
 uint64_t pir_epoch(const pir_db *db) { return db ? db->epoch : 0; }
 
+int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch)
+{
+    if (!db || levels > PREP_MAX_LEVELS)
+        return PIR_EINVAL;
+    if (levels && (db->bucket_bytes % (16ull << levels) != 0))
+        return PIR_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(db->mu);
+    HIP_TRY(hipSetDevice(db->device));
+    if (db->prep) {
+        // the reads still using the old leaves finish before they go
+        PIR_TRY(wait_readers(db, 2, db->stream));
+        HIP_TRY(hipStreamSynchronize(db->stream));
+        HIP_TRY(hipFree(db->prep));
+        db->prep = nullptr;
+        db->prep_levels = 0;
+    }
+    if (levels == 0)
+        return PIR_OK;
+    PrepTables t;
+    if (!prep_tables(levels, &t))
+        return PIR_EINVAL;
+    const uint64_t unit = 32ull << levels;
+    const uint64_t Nq = (db->n + unit - 1) / unit * unit >> levels;
+    const uint32_t Cq = (uint32_t)(db->bucket_bytes >> levels);
+    const uint64_t leaf_bytes = (padded_db_rows(Nq) * Cq + 255) & ~255ull;
+    void *p = nullptr;
+    if (hipMalloc(&p, leaf_bytes * t.leaves) != hipSuccess) {
+        (void)hipGetLastError();
+        return PIR_ENOMEM;
+    }
+    db->prep = static_cast<uint8_t *>(p);
+    db->prep_t = t;
+    db->prep_levels = levels;
+    db->prep_min_batch = min_batch ? min_batch : (256u << levels);
+    db->prep_leaf_bytes = leaf_bytes;
+    db->prep_Nq = Nq;
+    db->prep_Cq = Cq;
+    // rows past Nq of every leaf stay zero (the kernels may read them)
+    HIP_TRY(launch_fill_zero(db->prep, leaf_bytes * t.leaves, db->stream));
+    PIR_TRY(build_prep(db, db->front));
+    HIP_TRY(hipEventRecord(db->published, db->stream));
+    return PIR_OK;
+}
+
 // Next timing event pair for a read, or {nullptr, nullptr} when timing is
 // off or the record is full.
 static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
@@ -601,6 +662,53 @@ static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
     return PIR_OK;
 }
 
+// Preprocessed read of B request rows q (device, pitch qp, 4-byte aligned
+// words) into out (pitch op): the request blocks of every leaf, the 7^L leaf
+// products with the Four-Russians kernels, then the answers from the
+// products (masked in place when keys are given). `done` is recorded by the
+// last kernel; eb / ee take the start of the first leaf's main kernel and
+// the end of the last one's.
+static int prep_read(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, void *out, uint64_t op,
+                     const uint32_t *keys, hipStream_t s, hipEvent_t eb, hipEvent_t ee, hipEvent_t done)
+{
+    const PrepTables &t = db->prep_t;
+    const uint32_t Bq = (B + t.grid - 1) / t.grid;
+    const uint64_t Nq = db->prep_Nq, Wq = Nq / 32;
+    const uint32_t Cq = db->prep_Cq;
+    const uint64_t qpl = (Wq * 4 + 15) & ~15ull;        // leaf request pitch
+    const uint64_t q_leaf = ((uint64_t)Bq * qpl + 255) & ~255ull;
+    const uint64_t o_leaf = ((uint64_t)Bq * Cq + 255) & ~255ull;
+    PIR_TRY(ensure_device(&sc.leaf_q, &sc.leaf_q_cap, q_leaf * t.leaves));
+    PIR_TRY(ensure_device(&sc.leaf_out, &sc.leaf_out_cap, o_leaf * t.leaves));
+    HIP_TRY(launch_prep_q(t, q, qp, B, db->n, Bq, Wq, sc.leaf_q, qpl, q_leaf, s));
+    ReadGeom g{};
+    g.n = Nq;
+    g.stride = Cq;
+    g.qpitch = qpl;
+    g.B = Bq;
+    g.out_pitch = Cq;
+    Plan want = db->forced;
+    if (want.kind == KIND_AUTO) {
+        Plan tuned;
+        if (tune_lookup(Nq, Bq, Cq, &tuned))
+            want = tuned;
+    }
+    const Plan p = resolve_plan(g, want, db->num_cus);
+    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
+    for (uint32_t l = 0; l < t.leaves; ++l) {
+        g.D = db->prep + l * db->prep_leaf_bytes;
+        g.Q = static_cast<uint8_t *>(sc.leaf_q) + l * q_leaf;
+        g.out = static_cast<uint8_t *>(sc.leaf_out) + l * o_leaf;
+        HIP_TRY(launch_read(g, p, sc.part, s, l == 0 ? eb : nullptr, l + 1 == t.leaves ? ee : nullptr));
+    }
+    HIP_TRY(launch_prep_out(t, sc.leaf_out, o_leaf, B, Bq, Cq, out, op, s, keys ? nullptr : done));
+    if (keys)
+        HIP_TRY(launch_mask_rows(nullptr, 0, B, db->stride, out, op, keys, s, done));
+    return PIR_OK;
+}
+
+static bool use_prep(const pir_db *db, uint32_t B) { return db->prep && B >= db->prep_min_batch; }
+
 // Synchronous read (host rows in and out); seeds = B x 32 bytes of mask
 // seeds, or NULL for the plain answers.
 static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint8_t *seeds, uint8_t *resp)
@@ -618,11 +726,15 @@ static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint
         HIP_TRY(hipMemcpyAsync(sc.keys, seeds, (uint64_t)B * 32, hipMemcpyHostToDevice, db->stream));
         g.keys = static_cast<const uint32_t *>(sc.keys);
     }
-    Plan p = choose_plan(db, B);
-    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
     hipEvent_t eb, ee;
     PIR_TRY(profile_slot(db, &eb, &ee));
-    HIP_TRY(launch_read(g, p, sc.part, db->stream, eb, ee));
+    if (use_prep(db, B)) {
+        PIR_TRY(prep_read(db, sc, sc.req, db->qpitch, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
+    } else {
+        Plan p = choose_plan(db, B);
+        PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
+        HIP_TRY(launch_read(g, p, sc.part, db->stream, eb, ee));
+    }
     HIP_TRY(hipMemcpy2DAsync(resp, db->bucket_bytes, sc.resp, db->stride, db->bucket_bytes, B,
                              hipMemcpyDeviceToHost, db->stream));
     HIP_TRY(hipStreamSynchronize(db->stream));
@@ -660,14 +772,19 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     }
     ReadGeom g = read_geom(db, q, qp, B, out, op);
     g.keys = static_cast<const uint32_t *>(d_keys);
-    Plan p = choose_plan(db, B);
-    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
     hipEvent_t eb, ee, done;
     PIR_TRY(profile_slot(db, &eb, &ee));
-    PIR_TRY(reader_event(db, db->front, s, &done));
-    if (direct)
-        g.done = done;  // the read's last kernel marks the end of its use of the snapshot
-    HIP_TRY(launch_read(g, p, sc.part, s, eb, ee));
+    const bool prep = use_prep(db, B);
+    PIR_TRY(reader_event(db, prep ? 2 : db->front, s, &done));
+    if (prep) {
+        PIR_TRY(prep_read(db, sc, q, qp, B, out, op, g.keys, s, eb, ee, direct ? done : nullptr));
+    } else {
+        Plan p = choose_plan(db, B);
+        PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
+        if (direct)
+            g.done = done;  // the read's last kernel marks the end of its use of the snapshot
+        HIP_TRY(launch_read(g, p, sc.part, s, eb, ee));
+    }
     if (direct)
         return PIR_OK;
     HIP_TRY(hipMemcpy2DAsync(d_resp, resp_pitch, sc.resp, db->stride, db->bucket_bytes, B,

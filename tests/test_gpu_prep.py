@@ -1,0 +1,90 @@
+"""GPU parity of preprocessed (Strassen) reads against the CPU oracle.
+
+The preprocessed path computes the same GF(2) product as the plain read by
+another route (leaf databases formed at commit, 7^L leaf products, answers
+XORed together); every answer must equal the plain definition bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2001_08250_amd as pir
+import synth
+from helpers import assert_rows_equal, gpu_available
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("n,d,z", [(2000, 2, 128), (4096, 4, 64), (333, 1, 64)])
+def test_preprocessed_reads_match_oracle(levels, n, d, z):
+    """Ragged n (block rows padded with zero buckets), B below, at and above
+    multiples of 2^L (padded request rows), synchronous and async reads."""
+    import torch
+    D = synth.uniform_db(300 + n, n, d * z)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=1)
+        for B in (1, 3, 64, 301):
+            req = synth.bernoulli_requests(400 + B, B, n)
+            want = oracle.pir_read(D, req)
+            assert_rows_equal(db.read(req), want, f"L={levels} B={B} sync")
+            q = torch.from_numpy(req).cuda()
+            out = torch.zeros((B, d * z), dtype=torch.uint8, device="cuda")
+            db.read_async(q, out)
+            torch.cuda.synchronize()
+            assert_rows_equal(out.cpu().numpy(), want, f"L={levels} B={B} async")
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_preprocessed_reads_follow_epochs_and_masks(levels):
+    """Commits that change the snapshot rebuild the leaves: reads after each
+    commit see its data; masked reads give the masked answers; one-hot
+    requests return single buckets; levels 0 returns to the plain path."""
+    n, d, z, B = 1024, 2, 128, 96
+    rng = np.random.default_rng(7 + levels)
+    D = synth.uniform_db(500, n, d * z)
+    req = synth.bernoulli_requests(501, B, n)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=B)
+        for e in range(3):
+            published = D.copy()
+            for b in rng.choice(n, size=17, replace=False):
+                D[b] = rng.integers(0, 256, d * z, dtype=np.uint8)
+                db.write_bucket(int(b), D[b])
+            assert_rows_equal(db.read(req), oracle.pir_read(published, req), "staged, not yet published")
+            db.commit()
+            assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"epoch {e}")
+        seeds = synth.uniform_bytes(502, B * 32).reshape(B, 32)
+        assert_rows_equal(db.read_masked(req, seeds), oracle.pir_read_masked(D, req, seeds), "masked")
+        onehot = np.zeros((B, (n + 7) // 8), dtype=np.uint8)
+        for r in range(B):
+            j = (r * 37) % n
+            onehot[r, j >> 3] = 1 << (j & 7)
+        got = db.read(onehot)
+        for r in range(B):
+            assert np.array_equal(got[r], D[(r * 37) % n]), f"one-hot row {r}"
+        db.preprocess(0)
+        assert_rows_equal(db.read(req), oracle.pir_read(D, req), "plain path again")
+
+
+def test_preprocess_rejects_bad_levels_and_shapes():
+    """Blocks of buckets must be whole multiples of 16 bytes: 16 << levels
+    must divide d * msg_bytes; at most two levels."""
+    with pir.PirDB(64, 1, 24) as db:                # 24-byte buckets
+        with pytest.raises(pir.PirError):
+            db.preprocess(1)
+    with pir.PirDB(64, 1, 32) as db:                # 32-byte buckets: one level only
+        with pytest.raises(pir.PirError):
+            db.preprocess(3)
+        with pytest.raises(pir.PirError):
+            db.preprocess(2)
+        db.preprocess(1)
+        db.preprocess(0)
