@@ -206,8 +206,16 @@ enum pir_kernel_kind {
  * request offsets are fetched during the current one. PAIRS (M4R_WIDE): two
  * 5-bucket tables of 32 entries per step instead of one 6-bucket table,
  * each request folding both lookups in with one 3-input XOR per dword
- * (rolling lookups always). */
-enum { PIR_PLAN_SHARED_COLUMN = 1, PIR_PLAN_ROLLING = 1 << 12, PIR_PLAN_PAIRS = 1 << 13 };
+ * (rolling lookups always). PAIR_G4 / PAIR_G3 (with PAIRS): paired tables of
+ * 4 or 3 buckets (16 or 8 entries, 64 or 32 KiB of LDS double-buffered, two
+ * workgroups per CU) for batches of tens of requests. */
+enum {
+    PIR_PLAN_SHARED_COLUMN = 1,
+    PIR_PLAN_ROLLING = 1 << 12,
+    PIR_PLAN_PAIRS = 1 << 13,
+    PIR_PLAN_PAIR_G4 = 1 << 14,
+    PIR_PLAN_PAIR_G3 = 2 << 14
+};
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
  * splits (0 = heuristic), unroll (MASK/SKIP: buckets loaded ahead; M4R:

@@ -27,6 +27,8 @@ KERNEL_AUTO, KERNEL_MASK, KERNEL_SKIP, KERNEL_M4R, KERNEL_M4R_WIDE = 0, 1, 2, 3,
 PLAN_SHARED_COLUMN = 1
 PLAN_ROLLING = 1 << 12
 PLAN_PAIRS = 1 << 13
+PLAN_PAIR_G4 = 1 << 14     # with PLAN_PAIRS: 4-bucket tables
+PLAN_PAIR_G3 = 2 << 14     # with PLAN_PAIRS: 3-bucket tables
 PROFILE_MAX = 4096
 IV_DEFAULT_BITS, IV_DEFAULT_WINDOW = 1 << 17, 100   # the library's interest-vector defaults
 

@@ -48,6 +48,8 @@ struct Plan {
 };
 constexpr uint32_t PLAN_SHARED_COLUMN = 1;
 constexpr uint32_t PLAN_ROLLING = 1u << 12;
+// paired tables of 5 - ((flags >> PLAN_PAIR_G_SHIFT) & 3) buckets each (5, 4 or 3)
+constexpr uint32_t PLAN_PAIR_G_SHIFT = 14;
 constexpr uint32_t PLAN_PAIRS = 1u << 13;
 
 // Device scratch the read needs for split partials: bytes.

@@ -57,15 +57,24 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
     if (p.kind == KIND_AUTO) {
-        // Small batches stream D with the plain tile kernels; larger ones
-        // share paired 5-bucket Four-Russians tables among up to 256
-        // requests per workgroup (below about 64 requests the table builds
-        // cost more than they save).
-        if (g.B >= 64) {
+        // Small batches stream D with the plain tile kernels. Above 16
+        // requests, paired Four-Russians tables shared by the requests of a
+        // workgroup win: 4-bucket tables (two workgroups per CU) for one
+        // workgroup of up to 128 requests, 5-bucket tables (one workgroup of
+        // up to 256 requests per CU) above, where their fewer lookups per
+        // request outweigh the larger table builds. A request tile covers
+        // the whole batch up to 256 requests (a second tile would build
+        // every table again).
+        if (g.B > 128) {
             p.kind = KIND_M4RW;
             p.flags = PLAN_PAIRS;
             p.unroll = 8;
-            p.tile = g.B >= 192 ? 32 : g.B >= 96 ? 16 : 8;
+            p.tile = 32;
+        } else if (g.B > 16) {
+            p.kind = KIND_M4RW;
+            p.flags = PLAN_PAIRS | (1u << PLAN_PAIR_G_SHIFT);
+            p.unroll = 8;
+            p.tile = g.B > 64 ? 16 : g.B > 32 ? 8 : 4;
         } else {
             p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
         }
@@ -88,7 +97,9 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         if (p.unroll == 0)
             p.unroll = 8;
         units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
-        per_cu = 1;  // the two 64 KiB tables fill a CU's LDS
+        // double-buffered tables of 128 KiB fill a CU's LDS; paired 4- and
+        // 3-bucket tables (64 / 32 KiB) let two workgroups share it
+        per_cu = ((p.flags & PLAN_PAIRS) && ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u)) ? 2 : 1;
     } else {
         if (p.tile == 0)
             p.tile = g.B <= 16 ? pow2_at_least(std::max<uint32_t>(g.B, 1)) : 16;

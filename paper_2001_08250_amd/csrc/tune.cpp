@@ -118,8 +118,9 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
     }
     for (uint32_t nw : {4u, 8u, 16u})
     for (uint32_t fl : {2u << 8, 3u << 8, 4u << 8, PLAN_ROLLING, PLAN_ROLLING | (3u << 8), PLAN_PAIRS,
-                        PLAN_PAIRS | (3u << 8)}) {
-        for (uint32_t t : {8u, 16u, 32u}) {
+                        PLAN_PAIRS | (3u << 8), PLAN_PAIRS | (1u << PLAN_PAIR_G_SHIFT),
+                        PLAN_PAIRS | (2u << PLAN_PAIR_G_SHIFT)}) {
+        for (uint32_t t : {4u, 8u, 16u, 32u}) {
             if (t * nw > 8 * std::max<uint32_t>(B, 32))
                 continue;
             Plan base = resolve_plan(g, Plan{KIND_M4RW, t, 0, nw, fl}, db->num_cus);

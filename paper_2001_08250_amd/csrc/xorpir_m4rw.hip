@@ -279,30 +279,37 @@ void xorpir_m4rw_kernel(const WideArgs a)
     }
 }
 
-// ---- Paired 5-bucket tables -------------------------------------------
+// ---- Paired G-bucket tables -------------------------------------------
 //
-// A step covers 10 buckets ("pair" y: buckets 10y .. 10y+9) as two 5-bucket
-// tables A (10y .. 10y+4) and B (10y+5 .. 10y+9) of 32 x 1 KiB entries each.
-// Every request looks up both tables and folds the two entries into its
+// A step covers 2G buckets ("pair" y: buckets 2Gy .. 2Gy+2G-1) as two
+// G-bucket tables A (the first G) and B (the next G) of 2^G x 1 KiB entries
+// each. Every request looks up both tables and folds the two entries into its
 // accumulator with one 3-input XOR per dword. Half of the waves load and build
-// table A, the other half table B, so each wave holds only 5 row slices per
-// pair in flight. Two sets of two tables (double buffering) fill 128 KiB of
-// LDS. Per request and pair: 2 address adds, 2 ds_read_b128 and 4 v_xor3 for
-// 10 x 4 units; one barrier per 10 buckets.
-constexpr int GP = 5;                       // buckets per table
-constexpr int EP = 1 << GP;                 // 32 entries
-constexpr int TABLEP_U4 = EP * 64;          // 32 KiB
-constexpr int SETP_U4 = 2 * TABLEP_U4;      // the two tables of a step
-constexpr int PAIR_BUCKETS = 2 * GP;
+// table A, the other half table B, so each wave holds only G row slices per
+// pair in flight. Two sets of two tables (double buffering) take 2^(G+2) KiB
+// of LDS: 128 KiB at G = 5 (large batches, one workgroup per CU), 64 / 32
+// KiB at G = 4 / 3 (batches of tens of requests, where smaller tables cost
+// fewer LDS writes per request and two workgroups share a CU). Per request
+// and pair: 2 address adds, 2 ds_read_b128 and 4 v_xor3 for 2G x 4 units;
+// one barrier per 2G buckets.
+template <int G>
+struct PairShape {
+    static constexpr int E = 1 << G;             // entries per table
+    static constexpr int TABLE_U4 = E * 64;      // E x 1 KiB
+    static constexpr int SET_U4 = 2 * TABLE_U4;  // the two tables of a step
+    static constexpr int BUCKETS = 2 * G;        // buckets per step
+    static constexpr int WGS = G == 5 ? 1 : 2;   // workgroups per CU
+};
 
-// The 5 row slices of one half (0 = A, 1 = B) of pair y for this lane
+// The G row slices of one half (0 = A, 1 = B) of pair y for this lane
 // (rows past n are readable padding and only meet zero request bits).
-__device__ __forceinline__ void load_half(uint4 (&d)[GP], const uint8_t *__restrict__ D, uint64_t row_bytes,
+template <int G>
+__device__ __forceinline__ void load_half(uint4 (&d)[G], const uint8_t *__restrict__ D, uint64_t row_bytes,
                                           uint32_t lane_off, uint64_t y, uint32_t half)
 {
-    const uint8_t *row = D + (y * PAIR_BUCKETS + half * GP) * row_bytes;
+    const uint8_t *row = D + (y * (2 * G) + half * G) * row_bytes;
 #pragma unroll
-    for (int i = 0; i < GP; ++i) {
+    for (int i = 0; i < G; ++i) {
         d[i] = *reinterpret_cast<const uint4 *>(row + lane_off);
         row += row_bytes;
     }
@@ -310,11 +317,12 @@ __device__ __forceinline__ void load_half(uint4 (&d)[GP], const uint8_t *__restr
 
 // Wave wt of the WPT waves that build one table writes entries (wt << LB) | x,
 // x < 2^LB, in Gray code order.
-template <int WPT>
-__device__ __forceinline__ void build_half(uint4 *__restrict__ tbl, const uint4 (&d)[GP], uint32_t wt, uint32_t lane)
+template <int WPT, int G>
+__device__ __forceinline__ void build_half(uint4 *__restrict__ tbl, const uint4 (&d)[G], uint32_t wt, uint32_t lane)
 {
     constexpr int LW = log2_waves<WPT>();
-    constexpr int LB = GP - LW;
+    constexpr int LB = G - LW;
+    static_assert(LB >= 0, "more building waves than table entries");
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
     for (int b = 0; b < LW; ++b)
@@ -372,17 +380,18 @@ __device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *se
 // wave's half of pair y (already built) and is refilled with pair y + P; the
 // half of pair y + 1 in ring[(K + 1) % P] is built into the other set; pair
 // y is looked up; the next pair's offsets are fetched; barrier.
-template <int NW, int TW, int P, int K>
-__device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW],
+template <int NW, int TW, int P, int K, int G>
+__device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW],
                                           uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
                                           uint32_t lane_off, uint64_t y, const uint32_t *__restrict__ Qw,
                                           uint32_t Bp, bool active, uint32_t half, uint32_t wt, uint32_t lane)
 {
+    using S = PairShape<G>;
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
-    load_half(ring[slot], D, row_bytes, lane_off, y + P, half);
-    build_half<NW / 2>(lds + (buf ^ 1) * SETP_U4 + half * TABLEP_U4, ring[next], wt, lane);
+    load_half<G>(ring[slot], D, row_bytes, lane_off, y + P, half);
+    build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
     if (active) {
-        lookup_pairs<TW, 4>(acc, reinterpret_cast<const uint8_t *>(lds + buf * SETP_U4 + lane), offs);
+        lookup_pairs<TW, (TW < 4 ? TW : 4)>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane), offs);
         // the next pair's offsets (rows r0 .. r0 + TW - 1 < Bp of pair
         // y + 1 <= pairs, inside the staging area); the index goes through
         // readfirstlane for the reason given in group_step
@@ -396,21 +405,22 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][GP]
     __syncthreads();
 }
 
-template <int NW, int TW, int P, int K, int U>
-__device__ __forceinline__ void pair_steps(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW], uint4 *lds,
+template <int NW, int TW, int P, int K, int U, int G>
+__device__ __forceinline__ void pair_steps(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW], uint4 *lds,
                                            const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
                                            uint64_t y, const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
                                            uint32_t half, uint32_t wt, uint32_t lane)
 {
     if constexpr (K < U) {
-        pair_step<NW, TW, P, K>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt, lane);
-        pair_steps<NW, TW, P, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, y, Qw, Bp, active, half, wt,
-                                        lane);
+        pair_step<NW, TW, P, K, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt,
+                                   lane);
+        pair_steps<NW, TW, P, K + 1, U, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y, Qw, Bp, active, half, wt,
+                                           lane);
     }
 }
 
-template <int NW, int TW, int P, int K, int U>
-__device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][GP], uint32_t (&offs)[TW],
+template <int NW, int TW, int P, int K, int U, int G>
+__device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW],
                                                 uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
                                                 uint32_t lane_off, uint64_t y, uint64_t left,
                                                 const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
@@ -418,22 +428,24 @@ __device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[
 {
     if constexpr (K < U) {
         if ((uint64_t)K < left) {
-            pair_step<NW, TW, P, K>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt,
-                                    lane);
-            pair_steps_tail<NW, TW, P, K + 1, U>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw, Bp,
-                                                 active, half, wt, lane);
+            pair_step<NW, TW, P, K, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half,
+                                       wt, lane);
+            pair_steps_tail<NW, TW, P, K + 1, U, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw, Bp,
+                                                    active, half, wt, lane);
         }
     }
 }
 
 // Same task layout and outputs as xorpir_m4rw_kernel; a.groups counts pairs.
-template <int NW, int TW, int P>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+template <int NW, int TW, int P, int G>
+__global__ __launch_bounds__(NW * 64)
+__attribute__((amdgpu_waves_per_eu(NW / 4 * PairShape<G>::WGS, NW / 4 * PairShape<G>::WGS)))
 void xorpir_m4rp_kernel(const WideArgs a)
 {
     static_assert(NW >= 4 && NW <= 16, "two tables built by NW / 2 waves each");
+    using S = PairShape<G>;
     constexpr int U = (P % 2 == 0) ? P : 2 * P;
-    __shared__ uint4 lds[2 * SETP_U4];
+    __shared__ uint4 lds[2 * S::SET_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
     if (t >= a.n_rt * a.slices * a.splits)
@@ -461,10 +473,10 @@ void xorpir_m4rp_kernel(const WideArgs a)
         acc[r] = make_uint4(0u, 0u, 0u, 0u);
 
     if (gb < ge) {
-        uint4 ring[P][GP];
+        uint4 ring[P][G];
 #pragma unroll
         for (int k = 0; k < P; ++k)
-            load_half(ring[k], a.D, a.row_bytes, lane_off, gb + k, half);
+            load_half<G>(ring[k], a.D, a.row_bytes, lane_off, gb + k, half);
         const uint32_t *Qw = a.Qs + r0;
         uint32_t offs[TW] = {};
         if (active) {
@@ -472,15 +484,15 @@ void xorpir_m4rp_kernel(const WideArgs a)
             for (int i = 0; i < TW; ++i)
                 offs[i] = Qw[gb * a.Bp + i];
         }
-        build_half<NW / 2>(lds + half * TABLEP_U4, ring[0], wt, lane);
+        build_half<NW / 2, G>(lds + half * S::TABLE_U4, ring[0], wt, lane);
         __syncthreads();
         uint64_t y = gb;
         for (; y + U <= ge; y += U)
-            pair_steps<NW, TW, P, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, Qw, a.Bp, active, half,
-                                        wt, lane);
+            pair_steps<NW, TW, P, 0, U, G>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, Qw, a.Bp, active,
+                                           half, wt, lane);
         if (y < ge)
-            pair_steps_tail<NW, TW, P, 0, U>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, ge - y, Qw, a.Bp,
-                                             active, half, wt, lane);
+            pair_steps_tail<NW, TW, P, 0, U, G>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, ge - y, Qw,
+                                                a.Bp, active, half, wt, lane);
     }
 
     if (active && col_ok) {
@@ -492,18 +504,20 @@ void xorpir_m4rp_kernel(const WideArgs a)
     }
 }
 
-// Qs[y * Bp + r] = (A << 16 ... ): for pair y and request row r, with a / b the
-// 5 request bits of tables A / B (bits >= n cleared), the low half holds
-// a * 1024 and the high half b * 1024 + 32 KiB (table B's offset within the
-// set). Rows B <= r < Bp and the extra pair y = pairs hold zero bits. One
-// thread per (chunk of 16 pairs, row): a chunk's 160 request bits are exactly
-// words 5c .. 5c+4 of the row.
+// Qs[y * Bp + r] = (B << 16) | A: for pair y and request row r, with a / b
+// the G request bits of tables A / B (bits >= n cleared), the low half holds
+// a * 1024 and the high half b * 1024 + 2^G KiB (table B's offset within the
+// set; below 64 KiB for G <= 5). Rows B <= r < Bp and the extra pair y = pairs
+// hold zero bits. One thread per (chunk of 16 pairs, row): a chunk's 32G
+// request bits are exactly words G c .. G c + G - 1 of the row.
 constexpr int PAIR_CHUNK = 16;
 
+template <int G>
 __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
                                                                  uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
                                                                  uint32_t Bp, uint64_t pairs)
 {
+    using S = PairShape<G>;
     const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint64_t chunks = (pairs + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
     const uint64_t c = t / Bp;
@@ -511,11 +525,11 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
     if (c >= chunks)
         return;
     const uint64_t nwords = (n + 31) >> 5;
-    uint32_t w[6];
+    uint32_t w[G + 1];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const uint64_t wi = c * 5 + j;
-        w[j] = (j < 5 && r < B && wi < nwords) ? Q[(uint64_t)r * qpitch_w + wi] : 0u;
+    for (int j = 0; j <= G; ++j) {
+        const uint64_t wi = c * G + j;
+        w[j] = (j < G && r < B && wi < nwords) ? Q[(uint64_t)r * qpitch_w + wi] : 0u;
     }
     const uint64_t y0 = c * PAIR_CHUNK;
 #pragma unroll
@@ -523,14 +537,14 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
         const uint64_t y = y0 + k;
         if (y > pairs)
             break;
-        const int j = (PAIR_BUCKETS * k) >> 5, sh = (PAIR_BUCKETS * k) & 31;
+        const int j = (S::BUCKETS * k) >> 5, sh = (S::BUCKETS * k) & 31;
         const uint64_t win = (uint64_t)w[j] | ((uint64_t)w[j + 1] << 32);
-        uint32_t v = (uint32_t)(win >> sh) & ((1u << PAIR_BUCKETS) - 1u);
-        const uint64_t bit = y * PAIR_BUCKETS;
-        if (bit + PAIR_BUCKETS > n)
+        uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
+        const uint64_t bit = y * S::BUCKETS;
+        if (bit + S::BUCKETS > n)
             v &= bit >= n ? 0u : (1u << (n - bit)) - 1u;
-        const uint32_t ta = (v & (EP - 1)) * ENTRY_BYTES;
-        const uint32_t tb = (v >> GP) * ENTRY_BYTES + TABLEP_U4 * 16;
+        const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
+        const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
         Qs[y * Bp + r] = (tb << 16) | ta;
     }
 }
@@ -603,26 +617,43 @@ WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
     return nullptr;
 }
 
-WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth)
+WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g)
 {
     if (depth == 0)
         depth = 2;
-    if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<4, 16, 2>;
-    if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<4, 32, 2>;
-    if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2>;
-    if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2>;
-    if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<8, 32, 2>;
-    if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rp_kernel<8, 32, 3>;
+    if (g == 5) {
+        if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<4, 16, 2, 5>;
+        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<4, 32, 2, 5>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 5>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 5>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 5>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 5>;
+        if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rp_kernel<8, 16, 4, 5>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<8, 32, 2, 5>;
+        if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rp_kernel<8, 32, 3, 5>;
+    } else if (g == 4) {
+        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 4>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 4>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 4>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 4>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 4>;
+    } else if (g == 3) {
+        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 3>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 3>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 3>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 3>;
+    }
     return nullptr;
 }
 
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
+uint32_t plan_pair_g(const Plan &p) { return 5u - ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u); }
 uint32_t plan_mode(const Plan &p) { return (p.flags & PLAN_ROLLING) ? 1u : 0u; }
 bool plan_pairs(const Plan &p) { return (p.flags & PLAN_PAIRS) != 0; }
 
 WideFn plan_fn(const Plan &p)
 {
-    return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p))
+    return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p), plan_pair_g(p))
                          : wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
 }
 
@@ -637,7 +668,11 @@ bool m4rw_plan_supported(const Plan &p) { return plan_fn(p) != nullptr; }
 // Table steps of a read: 6-bucket groups, or 10-bucket pairs.
 uint64_t m4rw_steps(uint64_t n, const Plan &p)
 {
-    return plan_pairs(p) ? (n + PAIR_BUCKETS - 1) / PAIR_BUCKETS : (n + GB - 1) / GB;
+    if (plan_pairs(p)) {
+        const uint64_t per = 2 * plan_pair_g(p);
+        return (n + per - 1) / per;
+    }
+    return (n + GB - 1) / GB;
 }
 
 uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p)
@@ -672,9 +707,13 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
         const uint32_t chunk = plan_pairs(p) ? PAIR_CHUNK : STAGE_CHUNK;
         const uint64_t threads = (a.groups + 1 + chunk - 1) / chunk * a.Bp;
         const dim3 grid((uint32_t)((threads + 255) / 256));
-        if (plan_pairs(p))
-            hipLaunchKernelGGL(stage_pair_offsets_kernel, grid, dim3(256), 0, stream,
-                               static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
+        if (plan_pairs(p)) {
+            const uint32_t G = plan_pair_g(p);
+            auto stage = G == 5 ? stage_pair_offsets_kernel<5>
+                                : G == 4 ? stage_pair_offsets_kernel<4> : stage_pair_offsets_kernel<3>;
+            hipLaunchKernelGGL(stage, grid, dim3(256), 0, stream, static_cast<const uint32_t *>(g.Q), g.qpitch / 4,
+                               g.B, g.n, qs, a.Bp, a.groups);
+        }
         else
             hipLaunchKernelGGL(stage_wide_offsets_kernel, grid, dim3(256), 0, stream,
                                static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);

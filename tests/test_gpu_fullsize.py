@@ -55,7 +55,9 @@ def test_cuckoo_filled_65536_full_parity():
                                        (pir.KERNEL_M4R_WIDE, 32, 8, 0), (pir.KERNEL_M4R_WIDE, 16, 16, 0),
                                        (pir.KERNEL_M4R_WIDE, 16, 16, R), (pir.KERNEL_M4R_WIDE, 32, 8, R),
                                        (pir.KERNEL_M4R_WIDE, 8, 4, R),
-                                       (pir.KERNEL_M4R_WIDE, 32, 8, pir.PLAN_PAIRS)):
+                                       (pir.KERNEL_M4R_WIDE, 32, 8, pir.PLAN_PAIRS),
+                                       (pir.KERNEL_M4R_WIDE, 16, 8, pir.PLAN_PAIRS | pir.PLAN_PAIR_G4),
+                                       (pir.KERNEL_M4R_WIDE, 8, 8, pir.PLAN_PAIRS | pir.PLAN_PAIR_G3)):
             db.set_plan(kind, tile, 0, unroll, fl)
             say(f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
             assert_rows_equal(db.read(req), want, f"kind={kind} tile={tile} unroll={unroll} flags={fl:#x}")
@@ -81,7 +83,8 @@ def test_large_batch_sampled_rows(key):
         _sampled(db, D, req, rows, f"{w.name} auto")
         for kind, tile, unroll, fl in ((pir.KERNEL_MASK, 16, 8, 0), (pir.KERNEL_M4R, 32, 16, 0),
                                        (pir.KERNEL_M4R_WIDE, 32, 8, 0), (pir.KERNEL_M4R_WIDE, 16, 16, pir.PLAN_ROLLING),
-                                       (pir.KERNEL_M4R_WIDE, 32, 8, pir.PLAN_PAIRS)):
+                                       (pir.KERNEL_M4R_WIDE, 32, 8, pir.PLAN_PAIRS),
+                                       (pir.KERNEL_M4R_WIDE, 16, 8, pir.PLAN_PAIRS | pir.PLAN_PAIR_G4)):
             db.set_plan(kind, tile, 0, unroll, fl)
             say(f"{w.name}: kind={kind} tile={tile}")
             _sampled(db, D, req, rows[:4], f"{w.name} kind={kind}")

@@ -57,9 +57,14 @@ def test_small_workload_every_tile_schedule(kind):
 M4R_SHAPES = [(4, 32), (4, 64), (8, 16), (8, 32), (8, 64), (16, 16), (16, 32)]
 _R, _P = pir.PLAN_ROLLING, pir.PLAN_PAIRS
 # (waves, requests per wave, flags = prefetch depth << 8 | lookup mode)
+_G4 = pir.PLAN_PAIRS | pir.PLAN_PAIR_G4   # paired 4-bucket tables
+_G3 = pir.PLAN_PAIRS | pir.PLAN_PAIR_G3   # paired 3-bucket tables
 WIDE_SHAPES = [(4, 32, 2 << 8), (8, 16, 2 << 8), (8, 16, 4 << 8), (8, 32, 2 << 8), (8, 32, 3 << 8), (16, 16, 2 << 8),
                (4, 8, _R), (4, 16, _R), (8, 8, _R), (8, 16, _R), (8, 16, _R | 3 << 8), (8, 32, _R), (16, 16, _R),
-               (4, 16, _P), (4, 32, _P), (8, 8, _P), (8, 16, _P), (8, 32, _P), (8, 32, _P | 3 << 8)]
+               (4, 16, _P), (4, 32, _P), (8, 8, _P), (8, 16, _P), (8, 32, _P), (8, 32, _P | 3 << 8),
+               (8, 4, _P | 4 << 8), (8, 8, _P | 4 << 8), (8, 16, _P | 4 << 8),
+               (8, 4, _G4), (8, 4, _G4 | 4 << 8), (8, 8, _G4), (8, 8, _G4 | 4 << 8), (8, 16, _G4),
+               (8, 4, _G3), (8, 4, _G3 | 4 << 8), (8, 8, _G3), (8, 8, _G3 | 4 << 8)]
 FOUR_RUSSIANS = ([(pir.KERNEL_M4R, (nw, tw, 0)) for nw, tw in M4R_SHAPES] +
                  [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES])
 
