@@ -375,9 +375,11 @@ uint64_t pir_cuckoo_live(const pir_cuckoo *c);
  *     by the tuned read kernel, and the responses plus the published global
  *     interest vector are copied back. Batches on different lanes overlap on
  *     the device; reads arriving meanwhile join the next batch.
- *   - Every epoch_s seconds the writes that have arrived are applied to the
- *     cuckoo table (with their interest bits) and published (pir_epoch_commit).
- *     A read is answered from the snapshot published when its batch launched;
+ *   - Writes are applied to the cuckoo table (with their interest bits) and
+ *     their buckets staged as they arrive, between batches; every epoch_s
+ *     seconds the staged writes are published (pir_epoch_commit), so a write
+ *     becomes readable at the first epoch boundary after its arrival. A read
+ *     is answered from the snapshot published when its batch launched;
  *     read_epoch reports which.
  *   - max_batch = 1 gives the one-launch-per-read baseline.
  * Latency of a read = device completion of its batch (response and interest

@@ -1,8 +1,8 @@
 // Serving loop with continuous batching over device lanes (see
 // pir_serve_run in talek_pir.h). One dispatcher thread: it admits arrived
 // reads while memory slots are free, launches the queued reads as a batch on
-// any free lane, retires finished lanes, and applies + publishes the arrived
-// writes at every epoch boundary.
+// any free lane, retires finished lanes, applies arrived writes to the
+// working copy as they come, and publishes them at every epoch boundary.
 #include <string.h>
 
 #include <algorithm>
@@ -215,8 +215,11 @@ extern "C" int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_conf
             }
         }
         double now = now_s();
-        // 2. epoch boundary: apply the arrived writes and publish
-        if (now >= next_epoch) {
+        // 2. apply the arrived writes to the working copy and stage their
+        //    buckets as they come (a few per pass, so reads keep flowing);
+        //    the next epoch boundary publishes them
+        {
+            bool wrote = false;
             while (next_write < tr->n_writes && tr->write_t[next_write] <= now) {
                 const uint64_t w = next_write++;
                 if (res->write_epoch)
@@ -233,9 +236,15 @@ extern "C" int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_conf
                 if (cfg->interest_k &&
                     (rc = pir_interest_add(db, tr->write_interest + w * cfg->interest_k, cfg->interest_k)) != PIR_OK)
                     return rc;
+                wrote = true;
             }
-            if (table && (rc = pir_cuckoo_stage(table, nullptr)) != PIR_OK)
+            if (wrote && table && (rc = pir_cuckoo_stage(table, nullptr)) != PIR_OK)
                 return rc;
+            if (wrote)
+                progress = true;
+        }
+        // 3. epoch boundary: publish
+        if (now >= next_epoch) {
             if ((rc = pir_epoch_commit(db, nullptr)) != PIR_OK)
                 return rc;
             epochs++;
@@ -243,14 +252,14 @@ extern "C" int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_conf
             progress = true;
             now = now_s();
         }
-        // 3. admit arrived reads while memory slots are free
+        // 4. admit arrived reads while memory slots are free
         while (next_read < tr->n_reads && tr->read_t[next_read] <= now && inflight < slots) {
             queue.push_back(next_read++);
             inflight++;
             progress = true;
         }
         max_queue = std::max<uint64_t>(max_queue, queue.size());
-        // 4. launch the queue on a free lane
+        // 5. launch the queue on a free lane
         if (!queue.empty()) {
             for (Lane &l : R.lanes) {
                 if (l.busy || queue.empty())
