@@ -57,7 +57,7 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
 {
     Plan p = want;
     if (p.kind == KIND_AUTO) {
-        // Small batches stream D with the plain tile kernels. Above 16
+        // Small batches stream D with the masked tile kernel. Above 16
         // requests, paired Four-Russians tables shared by the requests of a
         // workgroup win: 4-bucket tables (two workgroups per CU) for one
         // workgroup of up to 128 requests, 5-bucket tables (one workgroup of
@@ -76,7 +76,14 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
             p.unroll = 8;
             p.tile = g.B > 64 ? 16 : g.B > 32 ? 8 : 4;
         } else {
-            p.kind = g.B > 8 ? KIND_SKIP : KIND_MASK;
+            // masked XOR; from 4 to 8 requests the four waves of a workgroup
+            // share one 1 KiB column chunk (one wave's tile holds them all),
+            // which streams D faster than four chunks per workgroup
+            p.kind = KIND_MASK;
+            if (g.B >= 4 && g.B <= 8) {
+                p.flags = PLAN_SHARED_COLUMN;
+                p.unroll = 4;
+            }
         }
     }
     const uint64_t nwords = (g.n + 31) / 32;
