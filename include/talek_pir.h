@@ -447,8 +447,9 @@ int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
  *   min_batch: reads of B >= min_batch rows take the preprocessed path
  *              (pir_read_batch*, masked or not); 0 selects 256 << levels,
  *              where each leaf product still has a full Four-Russians tile.
- *              The uneven-batch stream and the serving loop keep the plain
- *              path.
+ *              The serving loop's batches go through pir_read_batch_async
+ *              and take it when they are that large; the uneven-batch
+ *              stream keeps the plain path.
  * Errors: PIR_EINVAL for levels > 2 or d * msg_bytes not a multiple of
  * 16 << levels; PIR_ENOMEM when the leaves do not fit. The leaves are built
  * from the published snapshot at once (stream-ordered; reads wait for them).
