@@ -88,3 +88,37 @@ def test_preprocess_rejects_bad_levels_and_shapes():
             db.preprocess(2)
         db.preprocess(1)
         db.preprocess(0)
+
+
+def test_stream_and_commits_with_preprocessing_on():
+    """With the leaves on, the uneven-batch stream (plain path) still answers
+    every batch from the published snapshot, and commits between streams
+    rebuild the leaves that a large read then uses."""
+    import torch
+    n, d, z = 2048, 2, 128
+    rng = np.random.default_rng(91)
+    D = synth.uniform_db(92, n, d * z)
+    sizes = np.array([5, 70, 300, 1], dtype=np.uint64)
+    pool = synth.bernoulli_requests(93, 400, n)
+    first = np.array([0, 10, 50, 399], dtype=np.uint64)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(1, min_batch=64)
+        q = torch.from_numpy(pool).cuda()
+        out = torch.zeros((int(sizes.sum()), d * z), dtype=torch.uint8, device="cuda")
+        for rep in range(2):
+            for b in rng.choice(n, size=9, replace=False):
+                D[b] = rng.integers(0, 256, d * z, dtype=np.uint8)
+                db.write_bucket(int(b), D[b])
+            db.commit()
+            out.zero_()
+            db.read_stream_async(q, sizes, out, req_first=first)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            row = 0
+            for k, s in enumerate(sizes):
+                s = int(s)
+                want = oracle.pir_read(D, pool[int(first[k]):int(first[k]) + s])
+                assert_rows_equal(got[row:row + s], want, f"rep {rep} batch {k} (B={s})")
+                row += s
+            assert_rows_equal(db.read(pool[:300]), oracle.pir_read(D, pool[:300]), f"rep {rep} leaves")

@@ -49,8 +49,10 @@ def _oracle_snapshots(pre, writes, write_epoch, first_epoch, last_epoch):
     return snaps
 
 
-@pytest.mark.parametrize("max_batch,lanes", [(64, 2), (1, 3), (256, 1)])
-def test_serving_matches_oracle_per_epoch(max_batch, lanes):
+@pytest.mark.parametrize("max_batch,lanes,prep", [(64, 2, 0), (1, 3, 0), (256, 1, 0), (64, 2, 1)])
+def test_serving_matches_oracle_per_epoch(max_batch, lanes, prep):
+    """prep = 1: batches of 8 or more reads go through one-level Strassen
+    leaves, rebuilt by every epoch commit while reads are in flight."""
     pre = synth.write_ops(501, 9000, N, Z)
     read_t, rows, pool, write_t = _trace(1500, 0.5, 600)
     writes = synth.write_ops(502, write_t.size, N, Z)
@@ -61,6 +63,8 @@ def test_serving_matches_oracle_per_epoch(max_batch, lanes):
         table.insert_many(*pre)
         table.stage()
         e0 = db.commit()
+        if prep:
+            db.preprocess(prep, min_batch=8)
         probe = np.arange(0, read_t.size, 3)
         say(f"serving {read_t.size} reads, {write_t.size} writes, batch<={max_batch}, lanes={lanes}")
         out = pir.serve(db, table, read_t=read_t, read_row=rows, req_pool=pool, write_t=write_t, writes=writes,
