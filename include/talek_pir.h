@@ -248,11 +248,14 @@ int pir_tune_save(const char *path);
 int pir_tune_load(const char *path);
 
 /*
- * Kernel timing. While enabled (on != 0), every read of this handle issued by
- * pir_read_batch or pir_read_batch_async records a HIP event pair on its
- * stream right around the main read kernel (not the request staging or the
- * split reduction), for the first PIR_PROFILE_MAX reads after the enable;
- * later reads are not recorded. Enabling clears earlier records.
+ * Kernel timing. While enabled (on != 0), every on-th read of this handle
+ * issued by pir_read_batch or pir_read_batch_async (on = 1: every read;
+ * counting from the enable, the first one included) takes the start and end
+ * times of its main read kernel's dispatch (not the request staging or the
+ * split reduction) as a HIP event pair on its stream, for the first
+ * PIR_PROFILE_MAX recorded reads after the enable; later reads are not
+ * recorded. Enabling (or disabling) clears earlier records. on < 0 ->
+ * PIR_EINVAL.
  * pir_profile_collect waits for the recorded reads to finish, writes up to
  * cap durations in milliseconds (in issue order) into ms, the number of
  * recorded reads into *count (may be NULL), and clears the records.

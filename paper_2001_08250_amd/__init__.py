@@ -333,8 +333,9 @@ class PirDB:
         _check(self._L.pir_get_plan(self.h, B, ctypes.byref(p)), "pir_get_plan")
         return p
 
-    def profile_enable(self, on: bool = True):
-        _check(self._L.pir_profile_enable(self.h, 1 if on else 0), "pir_profile_enable")
+    def profile_enable(self, on: bool = True, every: int = 1):
+        """Time the main read kernel of every `every`-th read from now on (False: stop)."""
+        _check(self._L.pir_profile_enable(self.h, max(1, int(every)) if on else 0), "pir_profile_enable")
 
     def profile_collect(self) -> np.ndarray:
         """Main read kernel durations (ms) of the reads since profile_enable."""

@@ -107,6 +107,8 @@ struct pir_db {
     void *mirror_map = nullptr;
     // kernel timing (pir_profile_*): event pairs, created on first use
     bool prof_on = false;
+    uint32_t prof_every = 1;        // record every prof_every-th read
+    uint64_t prof_count = 0;        // reads issued since the enable
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     size_t prof_used = 0;
     // compressed interest vectors: device scratch of the encoder

@@ -645,7 +645,7 @@ int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch)
 static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
 {
     *eb = *ee = nullptr;
-    if (!db->prof_on || db->prof_used >= PIR_PROFILE_MAX)
+    if (!db->prof_on || db->prof_used >= PIR_PROFILE_MAX || (db->prof_count++ % db->prof_every) != 0)
         return PIR_OK;
     if (db->prof_used == db->prof_ev.size()) {
         hipEvent_t a = nullptr, b = nullptr;
@@ -975,10 +975,12 @@ int pir_interest_vector_async(pir_db *db, void *d_out, uint64_t out_bytes, void 
 
 int pir_profile_enable(pir_db *db, int on)
 {
-    if (!db)
+    if (!db || on < 0)
         return PIR_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     db->prof_on = on != 0;
+    db->prof_every = on > 1 ? (uint32_t)on : 1u;
+    db->prof_count = 0;
     db->prof_used = 0;
     return PIR_OK;
 }

@@ -382,6 +382,12 @@ def test_kernel_timing_records_each_read():
         db.profile_enable(False)
         db.read_async(q, out)
         assert db.profile_collect().size == 0
+        db.profile_enable(True, every=3)           # reads 0, 3 and 6 of seven
+        for _ in range(7):
+            db.read_async(q, out)
+        ms = db.profile_collect()
+        assert ms.size == 3 and np.all(ms > 0)
+        db.profile_enable(False)
         torch.cuda.synchronize()
         assert_rows_equal(out.cpu().numpy(), want, "async read")
 
