@@ -459,6 +459,19 @@ int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
  */
 int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch);
 
+/*
+ * The leaf tables of an L-level preprocessing (levels 1 or 2; no handle, no
+ * device work), for inspection and tests. Leaf i < 7^L sums the a_cnt[i]
+ * request blocks a[4 i .. 4 i + a_cnt[i] - 1] and the d_cnt[i] database
+ * blocks d[4 i ..], each block written (row << 4) | col in the 2^L x 2^L
+ * grid; answer block b (row * 2^L + col, b < 4^L) is the XOR of the o_cnt[b]
+ * leaves o_leaf[16 b ..]. Caller arrays: a_cnt, d_cnt 49 bytes; a, d 196;
+ * o_cnt 16; o_leaf 256. *leaves receives 7^L. PIR_EINVAL for other levels or
+ * a NULL pointer.
+ */
+int pir_preprocess_tables(uint32_t levels, uint32_t *leaves, uint8_t *a_cnt, uint8_t *a, uint8_t *d_cnt, uint8_t *d,
+                          uint8_t *o_cnt, uint8_t *o_leaf);
+
 #ifdef __cplusplus
 }
 #endif

@@ -111,6 +111,7 @@ SIGNATURES = {
     "pir_interest_config": (ctypes.c_int, [_vp, _u64, _u32]),
     "pir_interest_add": (ctypes.c_int, [_vp, _vp, _u32]),
     "pir_preprocess": (ctypes.c_int, [_vp, _u32, _u32]),
+    "pir_preprocess_tables": (ctypes.c_int, [_u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pir_interest_vector": (ctypes.c_int, [_vp, _u8p, _u64]),
     "pir_interest_vector_async": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "pir_interest_vector_encoded": (ctypes.c_int, [_vp, _u8p, _u64, _u64p]),
@@ -200,6 +201,23 @@ def xor_combine_async(out, ins, stream=None):
         raise ValueError("inputs must share shape and row pitch")
     _check(lib().pir_xor_combine_async(out.data_ptr(), op, ptrs, len(ins), ip, B, row, _stream_handle(stream)),
            "pir_xor_combine_async")
+
+
+def preprocess_tables(levels: int) -> dict:
+    """The Strassen leaf tables of `levels` levels (see pir_preprocess_tables)."""
+    leaves = np.zeros(1, dtype=np.uint32)
+    a_cnt, d_cnt = np.zeros(49, np.uint8), np.zeros(49, np.uint8)
+    a, d = np.zeros(196, np.uint8), np.zeros(196, np.uint8)
+    o_cnt, o_leaf = np.zeros(16, np.uint8), np.zeros(256, np.uint8)
+    _check(lib().pir_preprocess_tables(levels, _addr(leaves), _addr(a_cnt), _addr(a), _addr(d_cnt), _addr(d),
+                                       _addr(o_cnt), _addr(o_leaf)), "pir_preprocess_tables")
+    L = int(leaves[0])
+    g = 1 << levels
+    unpack = lambda v: (int(v) >> 4, int(v) & 15)
+    return {"grid": g,
+            "a": [[unpack(x) for x in a[4 * i:4 * i + int(a_cnt[i])]] for i in range(L)],
+            "d": [[unpack(x) for x in d[4 * i:4 * i + int(d_cnt[i])]] for i in range(L)],
+            "out": [[int(x) for x in o_leaf[16 * b:16 * b + int(o_cnt[b])]] for b in range(g * g)]}
 
 
 def _stream_handle(stream=None) -> int:

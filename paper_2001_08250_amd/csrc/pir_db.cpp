@@ -596,6 +596,22 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
 
 uint64_t pir_epoch(const pir_db *db) { return db ? db->epoch : 0; }
 
+int pir_preprocess_tables(uint32_t levels, uint32_t *leaves, uint8_t *a_cnt, uint8_t *a, uint8_t *d_cnt, uint8_t *d,
+                          uint8_t *o_cnt, uint8_t *o_leaf)
+{
+    PrepTables t;
+    if (!leaves || !a_cnt || !a || !d_cnt || !d || !o_cnt || !o_leaf || !prep_tables(levels, &t))
+        return PIR_EINVAL;
+    *leaves = t.leaves;
+    memcpy(a_cnt, t.a_cnt, sizeof t.a_cnt);
+    memcpy(a, t.a, sizeof t.a);
+    memcpy(d_cnt, t.d_cnt, sizeof t.d_cnt);
+    memcpy(d, t.d, sizeof t.d);
+    memcpy(o_cnt, t.o_cnt, sizeof t.o_cnt);
+    memcpy(o_leaf, t.o_leaf, sizeof t.o_leaf);
+    return PIR_OK;
+}
+
 int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch)
 {
     if (!db || levels > PREP_MAX_LEVELS)
