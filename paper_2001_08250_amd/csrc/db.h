@@ -27,6 +27,8 @@ struct Scratch {
     uint64_t aux_cap = 0;
     void *keys = nullptr;     // mask seeds of a synchronous masked read
     uint64_t keys_cap = 0;
+    void *host_rows = nullptr;  // synchronous reads: contiguous rows next to a host copy
+    uint64_t host_rows_cap = 0;
     void *leaf_q = nullptr;   // preprocessed reads: leaf requests and products
     uint64_t leaf_q_cap = 0;
     void *leaf_out = nullptr;

@@ -273,6 +273,7 @@ void free_db(pir_db *db)
         hipFree(kv.second.aux);
         hipFree(kv.second.keys);
         hipFree(kv.second.leaf_q);
+        hipFree(kv.second.host_rows);
         hipFree(kv.second.leaf_out);
     }
     for (int b = 0; b < 3; ++b)
@@ -734,9 +735,22 @@ static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint
     Scratch &sc = scratch_for(db, db->stream);
     PIR_TRY(ensure_device(&sc.req, &sc.req_cap, (uint64_t)B * db->qpitch));
     PIR_TRY(ensure_device(&sc.resp, &sc.resp_cap, (uint64_t)B * db->stride));
-    HIP_TRY(hipMemcpy2DAsync(sc.req, db->qpitch, req_bits, db->qbytes, db->qbytes, B, hipMemcpyHostToDevice,
-                             db->stream));
-    ReadGeom g = read_geom(db, sc.req, db->qpitch, B, sc.resp, db->stride);
+    // Host rows move in one contiguous copy each way (a pitched copy from or
+    // to pageable memory goes row by row); pitches change on the device.
+    const uint64_t qb = db->qbytes, in_bytes = (uint64_t)B * qb, out_bytes = (uint64_t)B * db->bucket_bytes;
+    const bool q_direct = qb % 4 == 0, r_direct = db->stride == db->bucket_bytes;
+    if (!q_direct || !r_direct)
+        PIR_TRY(ensure_device(&sc.host_rows, &sc.host_rows_cap, std::max(q_direct ? 0 : in_bytes,
+                                                                           r_direct ? 0 : out_bytes)));
+    uint64_t qp = qb;
+    if (q_direct) {
+        HIP_TRY(hipMemcpyAsync(sc.req, req_bits, in_bytes, hipMemcpyHostToDevice, db->stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(sc.host_rows, req_bits, in_bytes, hipMemcpyHostToDevice, db->stream));
+        HIP_TRY(hipMemcpy2DAsync(sc.req, db->qpitch, sc.host_rows, qb, qb, B, hipMemcpyDeviceToDevice, db->stream));
+        qp = db->qpitch;
+    }
+    ReadGeom g = read_geom(db, sc.req, qp, B, sc.resp, db->stride);
     if (seeds) {
         PIR_TRY(ensure_device(&sc.keys, &sc.keys_cap, (uint64_t)B * 32));
         HIP_TRY(hipMemcpyAsync(sc.keys, seeds, (uint64_t)B * 32, hipMemcpyHostToDevice, db->stream));
@@ -745,14 +759,19 @@ static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint
     hipEvent_t eb, ee;
     PIR_TRY(profile_slot(db, &eb, &ee));
     if (use_prep(db, B)) {
-        PIR_TRY(prep_read(db, sc, sc.req, db->qpitch, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
+        PIR_TRY(prep_read(db, sc, sc.req, qp, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
     } else {
         Plan p = choose_plan(db, B);
         PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
         HIP_TRY(launch_read(g, p, sc.part, db->stream, eb, ee));
     }
-    HIP_TRY(hipMemcpy2DAsync(resp, db->bucket_bytes, sc.resp, db->stride, db->bucket_bytes, B,
-                             hipMemcpyDeviceToHost, db->stream));
+    if (r_direct) {
+        HIP_TRY(hipMemcpyAsync(resp, sc.resp, out_bytes, hipMemcpyDeviceToHost, db->stream));
+    } else {
+        HIP_TRY(hipMemcpy2DAsync(sc.host_rows, db->bucket_bytes, sc.resp, db->stride, db->bucket_bytes, B,
+                                 hipMemcpyDeviceToDevice, db->stream));
+        HIP_TRY(hipMemcpyAsync(resp, sc.host_rows, out_bytes, hipMemcpyDeviceToHost, db->stream));
+    }
     HIP_TRY(hipStreamSynchronize(db->stream));
     return PIR_OK;
 }
