@@ -184,7 +184,7 @@ def serve_bench(args, pir):
         ipos = synth.interest_positions(x["arrival_seed"] + rate + 4, write_t.size, x["interest_k"],
                                         x["interest_bits"])
         row = {"rate": rate, "reads": int(read_t.size), "writes": int(write_t.size)}
-        for mode, mb, lanes in (("batched", args.max_batch, 2), ("one_per_read", 1, 4)):
+        for mode, mb, lanes in (("batched", args.max_batch, args.lanes), ("one_per_read", 1, 4)):
             if mode == "one_per_read" and args.no_baseline:
                 continue
             # the one-launch-per-read baseline is given a shorter slice of the same trace
@@ -290,8 +290,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4a", "c4b", "c3b", "c5"])
     ap.add_argument("--duration", type=float, default=3.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--baseline-s", type=float, default=1.0, help="serving: seconds of the one-per-read baseline")
-    ap.add_argument("--max-batch", type=int, default=1024, help="serving: reads per launch")
+    ap.add_argument("--max-batch", type=int, default=256, help="serving: reads per launch (256: one request tile of the paired-table kernel)")
     ap.add_argument("--rates", type=int, nargs="*", default=[], help="serving: subset of the arrival rates")
+    ap.add_argument("--lanes", type=int, default=2, help="serving: batches in flight")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--batches", type=int, default=0, help="uneven stream: number of batches (default 500)")
     ap.add_argument("--step", default="", choices=["", "full", "read"],
