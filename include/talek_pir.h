@@ -194,7 +194,8 @@ enum pir_kernel_kind {
     PIR_KERNEL_MASK = 1,   /* branch-free masked XOR (one 3-input op per word) */
     PIR_KERNEL_SKIP = 2,   /* wave-uniform zero-skip of unselected buckets */
     PIR_KERNEL_M4R = 3,    /* Four-Russians: 8-bucket tables in LDS, 4 bytes per lane */
-    PIR_KERNEL_M4R_WIDE = 4 /* Four-Russians: 6-bucket tables in LDS, 16 bytes per lane */
+    PIR_KERNEL_M4R_WIDE = 4 /* Four-Russians: 6-bucket tables, or paired 5/4/3-bucket tables (PAIRS
+                               flags), in LDS, 16 bytes per lane */
 };
 
 /* Plan flags. SHARED_COLUMN (MASK and SKIP families): the four waves of a
@@ -229,7 +230,9 @@ typedef struct pir_plan {
 } pir_plan;
 
 /* Force a schedule for subsequent reads of this handle (kind AUTO restores
- * the automatic choice). PIR_EINVAL for an unsupported combination. */
+ * the automatic choice: MASK up to 16 requests, paired 4-bucket tables up to
+ * 128, paired 5-bucket tables above, unless the tuning table has an entry).
+ * PIR_EINVAL for an unsupported combination. */
 int pir_set_plan(pir_db *db, const pir_plan *plan);
 
 /* The schedule the next read of B rows would use. */
