@@ -377,9 +377,10 @@ __device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *se
 }
 
 // Pair step for pair y, K = (y - first pair) mod U: ring[K % P] held this
-// wave's half of pair y (already built) and is refilled with pair y + P; the
-// half of pair y + 1 in ring[(K + 1) % P] is built into the other set; pair
-// y is looked up; the next pair's offsets are fetched; barrier.
+// wave's half of pair y (already built) and is refilled with pair y + P;
+// pair y is looked up; the next pair's offsets are fetched; the half of pair
+// y + 1 in ring[(K + 1) % P] is built into the other set (before the lookups
+// for the shapes named below); barrier.
 template <int NW, int TW, int P, int K, int G>
 __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW],
                                           uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
@@ -388,8 +389,15 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
 {
     using S = PairShape<G>;
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
+    // The next table is built after this step's lookups: issued first, its
+    // LDS writes hold up every wave's reads (and so its XORs) at the start of
+    // the step. Where two workgroups share a CU (128 VGPRs each), the longer
+    // live ranges of that order spill from 16 requests per wave or 4 pairs
+    // of prefetch on; those shapes build first.
+    constexpr bool late_build = G == 5 || (TW <= 8 && P <= 2);
     load_half<G>(ring[slot], D, row_bytes, lane_off, y + P, half);
-    build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
+    if (!late_build)
+        build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
     if (active) {
         lookup_pairs<TW, (TW < 4 ? TW : 4)>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane), offs);
         // the next pair's offsets (rows r0 .. r0 + TW - 1 < Bp of pair
@@ -402,6 +410,8 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
         for (int i = 0; i < TW; ++i)
             offs[i] = qn[i];
     }
+    if (late_build)
+        build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
     __syncthreads();
 }
 
