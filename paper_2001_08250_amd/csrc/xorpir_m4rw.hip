@@ -392,14 +392,16 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
     // The next table is built after this step's lookups: issued first, its
     // LDS writes hold up every wave's reads (and so its XORs) at the start of
     // the step. Where two workgroups share a CU (128 VGPRs each), the longer
-    // live ranges of that order spill from 16 requests per wave or 4 pairs
-    // of prefetch on; those shapes build first.
-    constexpr bool late_build = G == 5 || (TW <= 8 && P <= 2);
+    // live ranges of that order fit with 2 pairs of prefetch (and, at 16
+    // requests per wave, 2 lookup pairs in flight instead of 4); deeper
+    // prefetch builds first.
+    constexpr bool late_build = G == 5 || P <= 2;
+    constexpr int in_flight = (G < 5 && TW >= 16) ? 2 : 4;
     load_half<G>(ring[slot], D, row_bytes, lane_off, y + P, half);
     if (!late_build)
         build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
     if (active) {
-        lookup_pairs<TW, (TW < 4 ? TW : 4)>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane), offs);
+        lookup_pairs<TW, in_flight>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane), offs);
         // the next pair's offsets (rows r0 .. r0 + TW - 1 < Bp of pair
         // y + 1 <= pairs, inside the staging area); the index goes through
         // readfirstlane for the reason given in group_step
