@@ -512,8 +512,10 @@ def main():
     if lds:
         lds["frac"] = round(lds["floor_ms"] / kern_ms, 4)   # of the LDS-bound floor
         roof["lds"] = lds
+    # both plain-method fractions, whichever bound applies
     roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
-                plain_xor_tops=round(alu_achieved, 3), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
+                hbm_frac=round(hbm_achieved / HBM_PEAK_GBS, 4), plain_xor_tops=round(alu_achieved, 3),
+                valu_frac=round(alu_achieved / VALU_PEAK_TOPS, 4), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
 
     cpu = None
     parity = None
