@@ -49,6 +49,12 @@ def test_validation_without_device():
     assert L.pir_xor_combine_async(16, 8, two, 2, 16, 1, 16, None) == pir.PIR_EINVAL   # pitch < row
     assert L.pir_profile_enable(None, 1) == pir.PIR_EINVAL
     assert L.pir_profile_collect(None, None, 0, None) == pir.PIR_EINVAL
+    assert L.pir_preprocess(None, 1, 0) == pir.PIR_EINVAL
+    buf = (ctypes.c_uint8 * 256)()
+    leaves = ctypes.c_uint32(0)
+    for bad in (0, 3):
+        assert L.pir_preprocess_tables(bad, ctypes.byref(leaves), buf, buf, buf, buf, buf, buf) == pir.PIR_EINVAL
+    assert L.pir_preprocess_tables(1, None, buf, buf, buf, buf, buf, buf) == pir.PIR_EINVAL
     L.pir_db_destroy(None)  # NULL-safe
 
 
