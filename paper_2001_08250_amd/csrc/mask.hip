@@ -130,6 +130,9 @@ uint32_t blocks_for(uint64_t threads) { return (uint32_t)std::max<uint64_t>(1, (
 
 }  // namespace
 
+hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
+
 hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
                             uint64_t out_pitch, const uint32_t *keys, hipStream_t stream, hipEvent_t done)
 {
@@ -137,6 +140,16 @@ hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, u
         return done ? hipEventRecord(done, stream) : hipSuccess;
     const uint32_t stride16 = (uint32_t)(stride / 16);
     const uint64_t threads = (uint64_t)B * stride16;
+    if (partials && splits > 1 && threads < 64ull * WG) {
+        // a small answer: fewer than 64 workgroups would each walk every
+        // split; the plain reduction spreads the splits over more threads,
+        // then the masks go on in place
+        hipError_t e = launch_xor_splits(partials, splits, B, stride, out, out_pitch, stream, nullptr);
+        if (e != hipSuccess)
+            return e;
+        partials = nullptr;
+        splits = 0;
+    }
     hipExtLaunchKernelGGL(mask_rows_kernel, dim3(blocks_for(threads)), dim3(WG), 0, stream, nullptr, done, 0,
                           static_cast<const uint4 *>(partials), (uint64_t)B * stride16, splits, B, stride16,
                           static_cast<uint4 *>(out), out_pitch / 16, keys);

@@ -183,25 +183,54 @@ __global__ __launch_bounds__(WG) void xorpir_tile_kernel(const TileArgs a)
     }
 }
 
-// resp[r][c] = XOR over s of partials[s][r][c]
+// resp[r][c] = XOR over s of partials[s][r][c]. A workgroup covers TI
+// consecutive 16-byte words; its WG / TI thread groups take every
+// (WG / TI)-th split from their own first one and combine their sums in LDS.
+// Few words and many splits (a batch of one request split over every bucket
+// range) thus still spread the partials over many threads.
+template <int TI>
 __global__ __launch_bounds__(WG) void xor_splits_kernel(const uint4 *__restrict__ P, uint64_t split16,
                                                         uint32_t splits, uint64_t count, uint32_t stride16,
                                                         uint4 *__restrict__ out, uint64_t out_row16)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= count)
-        return;
+    constexpr uint32_t TS = WG / TI;
+    const uint32_t t = threadIdx.x;
+    const uint32_t sg = t / TI;
+    const uint64_t i = (uint64_t)blockIdx.x * TI + t % TI;
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    if (i < count) {
 #pragma unroll 8
-    for (uint32_t s = 0; s < splits; ++s) {
-        const uint4 v = P[(uint64_t)s * split16 + i];
-        acc.x ^= v.x;
-        acc.y ^= v.y;
-        acc.z ^= v.z;
-        acc.w ^= v.w;
+        for (uint32_t s = sg; s < splits; s += TS) {
+            const uint4 v = P[(uint64_t)s * split16 + i];
+            acc.x ^= v.x;
+            acc.y ^= v.y;
+            acc.z ^= v.z;
+            acc.w ^= v.w;
+        }
     }
-    const uint64_t r = i / stride16, c = i % stride16;
-    out[r * out_row16 + c] = acc;
+    if constexpr (TS > 1) {
+        // groups [h, 2h) fold into groups [0, h); reads and writes of one
+        // round touch disjoint slots
+        __shared__ uint4 part[WG];
+        part[t] = acc;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t h = TS / 2; h >= 1; h /= 2) {
+            if (sg < h) {
+                const uint4 v = part[t + h * TI];
+                acc.x ^= v.x;
+                acc.y ^= v.y;
+                acc.z ^= v.z;
+                acc.w ^= v.w;
+                part[t] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    if (sg == 0 && i < count) {
+        const uint64_t r = i / stride16, c = i % stride16;
+        out[r * out_row16 + c] = acc;
+    }
 }
 
 using TileFn = void (*)(const TileArgs);
@@ -246,6 +275,18 @@ TileFn tile_fn(const Plan &p)
 
 bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
 
+// Words per workgroup of the split reduction: all 256 threads on distinct
+// words while that gives at least 1024 workgroups (four per CU); fewer words
+// per workgroup (at least 4, one 64-byte segment) and more threads per word
+// for smaller answers, as long as every thread group has a split.
+uint32_t split_reduce_items(uint64_t count, uint32_t splits)
+{
+    uint32_t ti = WG;
+    while (ti > 4 && (count + ti - 1) / ti < 1024 && 2ull * (WG / ti) <= splits)
+        ti /= 2;
+    return ti;
+}
+
 hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
                              uint64_t out_pitch, hipStream_t stream, hipEvent_t done)
 {
@@ -253,8 +294,19 @@ hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, 
     const uint64_t count = (uint64_t)B * stride16;
     if (count == 0)
         return done ? hipEventRecord(done, stream) : hipSuccess;
-    const uint32_t rgrid = (uint32_t)((count + WG - 1) / WG);
-    hipExtLaunchKernelGGL(xor_splits_kernel, dim3(rgrid), dim3(WG), 0, stream, nullptr, done, 0,
+    const uint32_t ti = split_reduce_items(count, splits);
+    void (*fn)(const uint4 *, uint64_t, uint32_t, uint64_t, uint32_t, uint4 *, uint64_t);
+    switch (ti) {
+    case 4: fn = xor_splits_kernel<4>; break;
+    case 8: fn = xor_splits_kernel<8>; break;
+    case 16: fn = xor_splits_kernel<16>; break;
+    case 32: fn = xor_splits_kernel<32>; break;
+    case 64: fn = xor_splits_kernel<64>; break;
+    case 128: fn = xor_splits_kernel<128>; break;
+    default: fn = xor_splits_kernel<WG>; break;
+    }
+    const uint32_t rgrid = (uint32_t)((count + ti - 1) / ti);
+    hipExtLaunchKernelGGL(fn, dim3(rgrid), dim3(WG), 0, stream, nullptr, done, 0,
                           static_cast<const uint4 *>(partials), count, splits, count, stride16,
                           static_cast<uint4 *>(out), out_pitch / 16);
     return hipGetLastError();

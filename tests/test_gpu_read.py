@@ -157,6 +157,29 @@ def test_ragged_shapes(n, d, z, B):
             assert_rows_equal(db.read(req), want, f"kind={kind} shared column")
 
 
+@pytest.mark.parametrize("n,d,z", [(65533, 4, 1024), (8190, 1, 16), (4000, 3, 20)])
+def test_split_reduction_small_answers_many_splits(n, d, z):
+    """The split reduction spreads many splits of a small answer over the
+    threads of a workgroup (LDS combine): every words-per-workgroup width it
+    picks, odd split counts, plain and masked answers."""
+    D = synth.uniform_db(n + 11, n, d * z)
+    nwords = (n + 31) // 32
+    with _db(D, d, z) as db:
+        for B in (1, 3, 6):
+            req = synth.bernoulli_requests(n + 17 * B, B, n)
+            seeds = synth.uniform_bytes(n + 19 * B, B * 32).reshape(B, 32)
+            want = oracle.pir_read(D, req, threads=8)
+            want_m = oracle.pir_read_masked(D, req, seeds, threads=8)
+            for s in sorted({nwords, nwords - 1, 513, 128, 127, 9, 2}):
+                if s < 1 or s > nwords:
+                    continue
+                say(f"n={n} bucket={d * z} B={B} splits={s}")
+                db.set_plan(pir.KERNEL_MASK, 1, s, 16)
+                assert_rows_equal(db.read(req), want, f"B={B} splits={s}")
+                assert_rows_equal(db.read_masked(req, seeds), want_m, f"masked B={B} splits={s}")
+        db.set_plan()
+
+
 def test_padding_bits_ignored_and_empty_batch():
     n, d, z = 37, 2, 32
     D = synth.uniform_db(41, n, d * z)
