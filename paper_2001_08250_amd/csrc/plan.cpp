@@ -23,6 +23,7 @@ uint64_t m4rw_steps(uint64_t n, const Plan &p);
 namespace {
 
 constexpr uint64_t PARTIAL_CAP = 256ull << 20;  // bytes of split partials per read
+constexpr uint64_t PARTIAL_SOFT = 64ull << 20;  // the tile kernels aim lower (or at 1/64 of D if larger)
 
 uint32_t pow2_at_least(uint32_t x)
 {
@@ -125,6 +126,18 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         const uint64_t per_split = (uint64_t)g.B * g.stride;
         if (per_split)
             s = std::min<uint64_t>(s, std::max<uint64_t>(PARTIAL_CAP / per_split, 1));
+        if (per_split && (p.kind == KIND_MASK || p.kind == KIND_SKIP)) {
+            // These kernels stream D at HBM speed, and every split adds a
+            // partial answer that is written and read again: halve the
+            // splits while the partials exceed 64 MiB and 1/64 of the
+            // snapshot, down to two workgroups per CU (at B = 16 over 4 GiB,
+            // 1024 splits ran 3% faster than 2048 and 512 7% slower; an
+            // uneven 1365 at B = 12 ran 7% slower than 2048).
+            const uint64_t cap = std::max<uint64_t>(PARTIAL_SOFT, g.n * g.stride / 64);
+            const uint64_t least = ((uint64_t)std::max(num_cus, 1) * 2 + units - 1) / std::max<uint64_t>(units, 1);
+            while (s * per_split > cap && s / 2 >= least)
+                s /= 2;
+        }
         p.splits = (uint32_t)std::max<uint64_t>(s, 1);
     }
     const uint64_t max_splits = p.kind == KIND_M4RW ? m4rw_steps(g.n, p) : nwords;
