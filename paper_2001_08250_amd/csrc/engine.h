@@ -106,6 +106,10 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t stream);       
 // rows (splits > 1), and apply the one-time masks when g.keys is set (fused
 // into that reduction, or in place on the rows when there were no splits).
 hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream);
+// out row r (pitch out_pitch) = XOR over s < splits of partials[s][r]
+// ([splits][B][stride] bytes); `done`, when set, is recorded by the kernel.
+hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
+                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
 hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
                             uint64_t out_pitch, const uint32_t *keys, hipStream_t stream, hipEvent_t done = nullptr);
 

@@ -130,9 +130,6 @@ uint32_t blocks_for(uint64_t threads) { return (uint32_t)std::max<uint64_t>(1, (
 
 }  // namespace
 
-hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
-
 hipError_t launch_mask_rows(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
                             uint64_t out_pitch, const uint32_t *keys, hipStream_t stream, hipEvent_t done)
 {

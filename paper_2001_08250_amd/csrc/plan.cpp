@@ -145,9 +145,6 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
     return p;
 }
 
-hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
-
 hipError_t launch_split_reduce(const void *partials, uint32_t splits, const ReadGeom &g, hipStream_t stream)
 {
     if (g.keys)

@@ -33,9 +33,6 @@
 
 namespace talek {
 
-hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
-
 namespace {
 
 constexpr int ENTRIES = 256;

@@ -23,9 +23,6 @@
 
 namespace talek {
 
-hipError_t launch_xor_splits(const void *partials, uint32_t splits, uint32_t B, uint64_t stride, void *out,
-                             uint64_t out_pitch, hipStream_t stream, hipEvent_t done);
-
 namespace {
 
 constexpr int GB = 6;                        // buckets per group
@@ -718,6 +715,8 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     {
         const uint32_t chunk = plan_pairs(p) ? PAIR_CHUNK : STAGE_CHUNK;
         const uint64_t threads = (a.groups + 1 + chunk - 1) / chunk * a.Bp;
+        if (threads > 0xffffffffull - 255)  // a launch holds fewer than 2^32 work-items
+            return hipErrorInvalidValue;
         const dim3 grid((uint32_t)((threads + 255) / 256));
         if (plan_pairs(p)) {
             const uint32_t G = plan_pair_g(p);
