@@ -112,33 +112,46 @@ __global__ __launch_bounds__(WG) void prep_d_kernel(const PrepTables t, const ui
 
 // Request-side leaf: out[row][w] = XOR over the leaf's blocks (i, j) of
 // word j * Wq + w of request row i * Bq + row; rows >= B and bits >= n read
-// as zero (no word wholly past bit n is read).
+// as zero (no word wholly past bit n is read). Grid: x over the words of a
+// row, y = leaf, z over the rows; a thread takes QR rows gridDim.z apart at
+// a time (independent loads in flight), and the leaves that read one request
+// row run next to each other.
+constexpr uint32_t QR = 4;
+
 __global__ __launch_bounds__(WG) void prep_q_kernel(const PrepTables t, const uint32_t *__restrict__ Q,
                                                     uint64_t qpitch_w, uint32_t B, uint64_t n, uint32_t Bq,
                                                     uint64_t Wq, uint32_t *__restrict__ out, uint64_t out_pitch_w,
                                                     uint64_t leaf_w)
 {
     const uint32_t leaf = blockIdx.y;
-    const uint64_t total = (uint64_t)Bq * Wq;
-    uint32_t *o = out + leaf * leaf_w;
     const int cnt = t.a_cnt[leaf];
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (uint64_t)gridDim.x * WG) {
-        const uint32_t row = (uint32_t)(i / Wq);
-        const uint64_t w = i % Wq;
-        uint32_t v = 0;
-        for (int e = 0; e < cnt; ++e) {
-            const uint32_t blk = t.a[leaf][e];
-            const uint64_t r = (uint64_t)(blk >> 4) * Bq + row;
-            const uint64_t sw = (blk & 15u) * Wq + w;
-            const uint64_t bit = sw * 32;
-            if (r < B && bit < n) {
-                uint32_t x = Q[r * qpitch_w + sw];
-                if (bit + 32 > n)
-                    x &= (1u << (n - bit)) - 1u;
-                v ^= x;
+    const uint32_t gz = gridDim.z;
+    uint32_t *o = out + leaf * leaf_w;
+    for (uint32_t row0 = blockIdx.z; row0 < Bq; row0 += gz * QR) {
+        for (uint64_t w = (uint64_t)blockIdx.x * WG + threadIdx.x; w < Wq; w += (uint64_t)gridDim.x * WG) {
+            uint32_t v[QR] = {};
+            for (int e = 0; e < cnt; ++e) {
+                const uint32_t blk = t.a[leaf][e];
+                const uint64_t sw = (blk & 15u) * Wq + w;
+                const uint64_t bit = sw * 32;
+                if (bit >= n)
+                    continue;
+                const uint32_t keep = bit + 32 > n ? (1u << (n - bit)) - 1u : ~0u;
+#pragma unroll
+                for (uint32_t k = 0; k < QR; ++k) {
+                    const uint32_t row = row0 + k * gz;
+                    const uint64_t r = (uint64_t)(blk >> 4) * Bq + row;
+                    if (row < Bq && r < B)
+                        v[k] ^= Q[r * qpitch_w + sw] & keep;
+                }
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < QR; ++k) {
+                const uint32_t row = row0 + k * gz;
+                if (row < Bq)
+                    o[(uint64_t)row * out_pitch_w + w] = v[k];
             }
         }
-        o[(uint64_t)row * out_pitch_w + w] = v;
     }
 }
 
@@ -226,7 +239,8 @@ hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, ui
 hipError_t launch_prep_q(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t Bq,
                          uint64_t Wq, void *out, uint64_t out_pitch, uint64_t leaf_bytes, hipStream_t stream)
 {
-    hipLaunchKernelGGL(prep_q_kernel, dim3(grid_for((uint64_t)Bq * Wq), t.leaves), dim3(WG), 0, stream, t,
+    const dim3 grid(grid_for(Wq), t.leaves, std::max<uint32_t>(1, std::min<uint32_t>((Bq + QR - 1) / QR, 64)));
+    hipLaunchKernelGGL(prep_q_kernel, grid, dim3(WG), 0, stream, t,
                        static_cast<const uint32_t *>(Q), qpitch / 4, B, n, Bq, Wq, static_cast<uint32_t *>(out),
                        out_pitch / 4, leaf_bytes / 4);
     return hipGetLastError();

@@ -517,9 +517,12 @@ void xorpir_m4rp_kernel(const WideArgs a)
 // the G request bits of tables A / B (bits >= n cleared), the low half holds
 // a * 1024 and the high half b * 1024 + 2^G KiB (table B's offset within the
 // set; below 64 KiB for G <= 5). Rows B <= r < Bp and the extra pair y = pairs
-// hold zero bits. One thread per (chunk of 16 pairs, row): a chunk's 32G
-// request bits are exactly words G c .. G c + G - 1 of the row.
-constexpr int PAIR_CHUNK = 16;
+// hold zero bits. A workgroup covers 64 rows and PAIR_CHUNK pairs, whose
+// 2G * PAIR_CHUNK request bits are exactly 4G words of each row: it loads
+// them row by row (consecutive threads on consecutive words) into LDS, rows
+// at an odd word stride, and each wave then writes a pair's 64 offsets per
+// store, one row per lane.
+constexpr int PAIR_CHUNK = 64;
 
 template <int G>
 __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
@@ -527,34 +530,44 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
                                                                  uint32_t Bp, uint64_t pairs)
 {
     using S = PairShape<G>;
-    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint64_t chunks = (pairs + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
-    const uint64_t c = t / Bp;
-    const uint32_t r = (uint32_t)(t % Bp);
-    if (c >= chunks)
-        return;
+    constexpr int W = PAIR_CHUNK * S::BUCKETS / 32;  // words per row and chunk (4G)
+    constexpr int RS = W + 1;                        // LDS row stride, odd
+    __shared__ uint32_t bits[64 * RS];
+    const uint32_t t = threadIdx.x;
+    const uint32_t r0 = blockIdx.y * 64;
+    const uint64_t w0 = (uint64_t)blockIdx.x * W;
     const uint64_t nwords = (n + 31) >> 5;
-    uint32_t w[G + 1];
 #pragma unroll
-    for (int j = 0; j <= G; ++j) {
-        const uint64_t wi = c * G + j;
-        w[j] = (j < G && r < B && wi < nwords) ? Q[(uint64_t)r * qpitch_w + wi] : 0u;
+    for (int k = 0; k < (64 * W + 255) / 256; ++k) {
+        const uint32_t i = t + 256u * k;
+        if (i < 64u * W) {
+            const uint32_t row = i / W, w = i % W;
+            const uint32_t r = r0 + row;
+            const uint64_t wi = w0 + w;
+            uint32_t v = 0u;
+            if (r < B && wi < nwords) {
+                v = Q[(uint64_t)r * qpitch_w + wi];
+                if (wi == nwords - 1 && (n & 31u))
+                    v &= (1u << (n & 31u)) - 1u;
+            }
+            bits[row * RS + w] = v;
+        }
     }
-    const uint64_t y0 = c * PAIR_CHUNK;
-#pragma unroll
-    for (int k = 0; k < PAIR_CHUNK; ++k) {
+    if (t < 64)
+        bits[t * RS + W] = 0u;  // the high word of the chunk's last window
+    __syncthreads();
+    const uint32_t wave = t >> 6, lane = t & 63u;
+    const uint64_t y0 = (uint64_t)blockIdx.x * PAIR_CHUNK;
+    for (uint32_t k = wave; k < PAIR_CHUNK; k += 4) {
         const uint64_t y = y0 + k;
         if (y > pairs)
             break;
-        const int j = (S::BUCKETS * k) >> 5, sh = (S::BUCKETS * k) & 31;
-        const uint64_t win = (uint64_t)w[j] | ((uint64_t)w[j + 1] << 32);
-        uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
-        const uint64_t bit = y * S::BUCKETS;
-        if (bit + S::BUCKETS > n)
-            v &= bit >= n ? 0u : (1u << (n - bit)) - 1u;
+        const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
+        const uint64_t win = (uint64_t)bits[lane * RS + j] | ((uint64_t)bits[lane * RS + j + 1] << 32);
+        const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
         const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
         const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
-        Qs[y * Bp + r] = (tb << 16) | ta;
+        Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
     }
 }
 
@@ -713,21 +726,23 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.groups = m4rw_steps(g.n, p);
     uint32_t *qs = static_cast<uint32_t *>(partials);
     {
-        const uint32_t chunk = plan_pairs(p) ? PAIR_CHUNK : STAGE_CHUNK;
-        const uint64_t threads = (a.groups + 1 + chunk - 1) / chunk * a.Bp;
-        if (threads > 0xffffffffull - 255)  // a launch holds fewer than 2^32 work-items
-            return hipErrorInvalidValue;
-        const dim3 grid((uint32_t)((threads + 255) / 256));
         if (plan_pairs(p)) {
+            const uint64_t chunks = (a.groups + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
+            if (chunks * 256 > 0xffffffffull)  // a grid dimension holds fewer than 2^32 work-items
+                return hipErrorInvalidValue;
             const uint32_t G = plan_pair_g(p);
             auto stage = G == 5 ? stage_pair_offsets_kernel<5>
                                 : G == 4 ? stage_pair_offsets_kernel<4> : stage_pair_offsets_kernel<3>;
-            hipLaunchKernelGGL(stage, grid, dim3(256), 0, stream, static_cast<const uint32_t *>(g.Q), g.qpitch / 4,
-                               g.B, g.n, qs, a.Bp, a.groups);
-        }
-        else
-            hipLaunchKernelGGL(stage_wide_offsets_kernel, grid, dim3(256), 0, stream,
+            hipLaunchKernelGGL(stage, dim3((uint32_t)chunks, a.Bp / 64), dim3(256), 0, stream,
                                static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
+        } else {
+            const uint64_t threads = (a.groups + 1 + STAGE_CHUNK - 1) / STAGE_CHUNK * a.Bp;
+            if (threads > 0xffffffffull - 255)  // a launch holds fewer than 2^32 work-items
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL(stage_wide_offsets_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0,
+                               stream, static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp,
+                               a.groups);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
