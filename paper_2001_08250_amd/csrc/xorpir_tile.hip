@@ -279,7 +279,7 @@ bool tile_plan_supported(const Plan &p) { return tile_fn(p) != nullptr; }
 // words while that gives at least 1024 workgroups (four per CU); fewer words
 // per workgroup (at least 4, one 64-byte segment) and more threads per word
 // for smaller answers, as long as every thread group has a split.
-uint32_t split_reduce_items(uint64_t count, uint32_t splits)
+static uint32_t split_reduce_items(uint64_t count, uint32_t splits)
 {
     uint32_t ti = WG;
     while (ti > 4 && (count + ti - 1) / ti < 1024 && 2ull * (WG / ti) <= splits)
