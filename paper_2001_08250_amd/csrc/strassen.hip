@@ -83,30 +83,39 @@ void expand(const Node &x, Node (&out)[7])
 
 // D-side leaf: out[row][c16] = XOR over the leaf's blocks (j, k) of
 // D[j * Nq + row][k * Cq16 + c16], rows j * Nq + row >= n reading as zero.
+// A workgroup takes RB = max(1, WG / Cq16) rows at a time: thread t owns
+// column t mod Cq16 (and every WG-th one after it when Cq16 > WG) of row
+// t / Cq16, so consecutive threads write consecutive 16-byte words. Grid:
+// x = leaf, y over the rows, so the leaves that read the same rows of D run
+// next to each other and share them through the caches.
 __global__ __launch_bounds__(WG) void prep_d_kernel(const PrepTables t, const uint4 *__restrict__ D,
                                                     uint64_t stride16, uint64_t n, uint64_t Nq, uint32_t Cq16,
                                                     uint4 *__restrict__ out, uint64_t leaf_u4)
 {
-    const uint32_t leaf = blockIdx.y;
-    const uint64_t total = Nq * Cq16;
+    const uint32_t leaf = blockIdx.x;
     uint4 *o = out + leaf * leaf_u4;
     const int cnt = t.d_cnt[leaf];
-    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (uint64_t)gridDim.x * WG) {
-        const uint64_t row = i / Cq16;
-        const uint32_t c16 = (uint32_t)(i % Cq16);
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        for (int e = 0; e < cnt; ++e) {
-            const uint32_t blk = t.d[leaf][e];
-            const uint64_t src = (blk >> 4) * Nq + row;
-            if (src < n) {
-                const uint4 x = D[src * stride16 + (blk & 15u) * Cq16 + c16];
-                v.x ^= x.x;
-                v.y ^= x.y;
-                v.z ^= x.z;
-                v.w ^= x.w;
+    const uint32_t rb = Cq16 >= WG ? 1u : WG / Cq16;
+    const uint32_t rr = Cq16 >= WG ? 0u : threadIdx.x / Cq16;
+    const uint32_t c0 = Cq16 >= WG ? threadIdx.x : threadIdx.x % Cq16;
+    if (rr >= rb)
+        return;
+    for (uint64_t row = (uint64_t)blockIdx.y * rb + rr; row < Nq; row += (uint64_t)gridDim.y * rb) {
+        for (uint32_t c16 = c0; c16 < Cq16; c16 += WG) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            for (int e = 0; e < cnt; ++e) {
+                const uint32_t blk = t.d[leaf][e];
+                const uint64_t src = (blk >> 4) * Nq + row;
+                if (src < n) {
+                    const uint4 x = D[src * stride16 + (blk & 15u) * Cq16 + c16];
+                    v.x ^= x.x;
+                    v.y ^= x.y;
+                    v.z ^= x.z;
+                    v.w ^= x.w;
+                }
             }
+            o[row * Cq16 + c16] = v;
         }
-        o[row * Cq16 + c16] = v;
     }
 }
 
@@ -230,7 +239,9 @@ hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, ui
                          void *out, uint64_t leaf_bytes, hipStream_t stream)
 {
     const uint32_t Cq16 = Cq / 16;
-    hipLaunchKernelGGL(prep_d_kernel, dim3(grid_for(Nq * Cq16), t.leaves), dim3(WG), 0, stream, t,
+    const uint32_t rb = Cq16 >= WG ? 1u : WG / Cq16;
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((Nq + rb - 1) / rb, 65535));
+    hipLaunchKernelGGL(prep_d_kernel, dim3(t.leaves, chunks), dim3(WG), 0, stream, t,
                        static_cast<const uint4 *>(D), stride / 16, n, Nq, Cq16, static_cast<uint4 *>(out),
                        leaf_bytes / 16);
     return hipGetLastError();
