@@ -34,6 +34,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SOURCES = ["pir_oracle.c", "cuckoo_oracle.c", "mask_oracle.c", "codec_oracle.c"]
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# A test may point the oracle at another build of these sources (the mutation
+# check builds deliberately broken copies to show that the pins catch them).
+LIB_PATH = os.environ.get("TALEK_ORACLE_LIB", LIB_PATH)
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
 
 _lib = None

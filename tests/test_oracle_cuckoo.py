@@ -22,7 +22,8 @@ def _payload(name, z):
     return p
 
 
-@pytest.mark.parametrize("which", ["gc_fifo_d2", "eviction_cycle_d1", "beta2_then_random_victim_d2"])
+@pytest.mark.parametrize("which", ["gc_fifo_d2", "eviction_cycle_d1", "beta2_then_random_victim_d2",
+                                   "three_evictions_d4", "three_evictions_d3"])
 def test_hand_worked_examples(golden_dir, which):
     g = json.load(open(os.path.join(golden_dir, "cuckoo_examples.json")))
     ex = next(e for e in g["examples"] if e["name"] == which)

@@ -43,6 +43,23 @@ def test_keystream_matches_openssl(seed):
     assert got.tobytes() == want
 
 
+@pytest.mark.parametrize("row_bytes", [4096, 520, 24])
+def test_mask_is_the_keystream_of_the_seed(row_bytes):
+    """The mask of a seed is the first row_bytes of ChaCha20 keyed by the seed,
+    all-zero nonce, block counter from 0: checked against the keystream
+    function (pinned above to the RFC and openssl) and, where installed,
+    against openssl directly."""
+    seeds = synth.uniform_bytes(row_bytes, 3 * 32).reshape(3, 32)
+    masks = oracle.apply_masks(np.zeros((3, row_bytes), dtype=np.uint8), seeds)
+    for r in range(3):
+        want = oracle.chacha20_stream(seeds[r].tobytes(), bytes(12), 0, row_bytes)
+        assert np.array_equal(masks[r], want)
+        if shutil.which("openssl"):
+            ref = subprocess.run(["openssl", "enc", "-chacha20", "-K", seeds[r].tobytes().hex(), "-iv", "00" * 16],
+                                 input=bytes(row_bytes), capture_output=True, check=True).stdout
+            assert masks[r].tobytes() == ref
+
+
 def test_masks_are_distinct_per_seed_and_position():
     seeds = synth.uniform_bytes(7, 2 * 32).reshape(2, 32)
     zero = np.zeros((2, 4096), dtype=np.uint8)
