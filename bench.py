@@ -1,17 +1,18 @@
 """Benchmark of the XOR-PIR server path on one MI355X.
 
-Default workload: n = 65,536 buckets of 4 x 1 KiB, filled by blocked-cuckoo
-insertion of 200,000 synthetic messages (load 0.763), answering batches of
-B = 256 Bernoulli(1/2) request vectors.
+Default workload: n = 2^22 buckets of 4 x 1 KiB (a 16 GiB database of uniform
+bytes), answering batches of B = 2048 Bernoulli(1/2) request vectors; then, as
+a second case in the same line ("extra"), n = 65,536 buckets filled by
+blocked-cuckoo insertion of 200,000 synthetic messages (256 MiB), B = 256.
 
 One step = one served batch through the whole server path: ceil(B/10) new
-Write requests (cuckoo insert with FIFO garbage collection + 6 interest bits
-each) staged and published as a new epoch, then the batch of B reads answered
-on that snapshot, then the global interest vector fetched. Inputs are
-resident (requests and writes prepared before the timed region). Prints ONE
-JSON line on stdout.
+Write requests (cuckoo insert with FIFO garbage collection, or whole-bucket
+writes for the uniform database; 6 interest bits each) staged and published
+as a new epoch, then the batch of B reads answered on that snapshot, then the
+global interest vector fetched. Inputs are resident (requests and writes
+prepared before the timed region). Prints ONE JSON line on stdout.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c4a|c4b|c3b] [--step full|read]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4a|c2|c1|c4b|c3b|c3|c5] [--step full|read]
 """
 from __future__ import annotations
 
@@ -30,7 +31,9 @@ import synth  # noqa: E402
 from synth import configs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0                      # MI355X HBM3E, published
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit VALU lane-ops per second: 39.3 T
+# 32-bit VALU lane-operations per second: 256 CUs x 128 lanes per clock x 2.4 GHz
+# = 78.6 T (the FP32 vector figure, 157.3 TFLOP/s, counts an FMA as two flops)
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # LDS rates measured by the roofline probe (bytes per clock and CU, 16-byte
 # accesses, no bank conflicts), at 256 CUs and 2.4 GHz
 LDS_READ_BPC, LDS_WRITE_BPC = 204.9, 75.4
@@ -75,6 +78,19 @@ def kernel_source_digest(kind: int) -> str:
     if not os.path.isfile(path):
         return ""
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_valu(workload: str, plan) -> float | None:
+    """VALU instructions per launch of the main read kernel (SQ_INSTS_VALU) from the
+    committed counter summary, or None when it does not match this plan and source."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
+    if not os.path.isfile(path):
+        return None
+    t = json.load(open(path))
+    want = {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll, "flags": plan.flags}
+    if t.get("plan") != want or t.get("kernel_source_sha256_16") != kernel_source_digest(plan.kind):
+        return None
+    return float(t["valu_insts_per_launch"])
 
 
 def measured_traffic(workload: str, plan) -> float | None:
@@ -147,6 +163,28 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str, calib_mib: 
         total += kib * factor * 1024
     out["hbm_bytes_per_launch"] = round(total)
     path = os.path.join(ROOT, "profiles", f"traffic_{out['workload']}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def valu_summary(pmc_dir: str, bench_json: str, command: str):
+    """Write profiles/valu_<workload>.json: VALU (and SALU, LDS) instructions per
+    launch of the main read kernel from one rocprofv3 --pmc pass (SQ_INSTS_VALU,
+    SQ_INSTS_SALU, SQ_INSTS_LDS, GRBM_GUI_ACTIVE) of the bench command."""
+    line = json.loads([x for x in open(bench_json) if x.startswith("{")][-1])
+    plan = line["config"]["plan"]
+    name = kernel_name(plan)
+    out = {"workload": line["config"]["workload"], "plan": plan,
+           "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name, "command": command}
+    for counter, key in (("SQ_INSTS_VALU", "valu_insts_per_launch"), ("SQ_INSTS_SALU", "salu_insts_per_launch"),
+                         ("SQ_INSTS_LDS", "lds_insts_per_launch"), ("GRBM_GUI_ACTIVE", "gui_active_per_launch")):
+        vals = [float(r["Counter_Value"]) for r in _counter_rows(pmc_dir, counter) if name in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"no {name} dispatches with {counter} in {pmc_dir}")
+        out[key] = float(np.mean(vals))
+        out["dispatches"] = len(vals)
+    path = os.path.join(ROOT, "profiles", f"valu_{out['workload']}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -285,9 +323,9 @@ def stream_bench(args, pir, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4a", "c4b", "c3b", "c5"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4a", choices=["c1", "c2", "c3", "c4a", "c4b", "c3b", "c5"])
     ap.add_argument("--duration", type=float, default=3.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--baseline-s", type=float, default=1.0, help="serving: seconds of the one-per-read baseline")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: reads per launch (256: one request tile of the paired-table kernel)")
@@ -307,7 +345,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="oracle rows on all host cores (default: every row up to 1 GiB databases, else 16)")
+    ap.add_argument("--cpu-rows-single", type=int, default=-1,
+                    help="oracle rows on one core (default: 2 over databases above 1 GiB, else 16)")
+    ap.add_argument("--latency-reads", type=int, default=20, help="batches issued alone for the latency figures")
+    ap.add_argument("--no-extra", action="store_true", help="c4a: skip the 256 MiB second case")
     ap.add_argument("--read-streams", type=int, default=1,
                     help="read streams that consecutive batches take in turn (1 = every batch on one stream)")
     ap.add_argument("--prep", type=int, default=0, choices=[0, 1, 2],
@@ -320,9 +363,14 @@ def main():
                     help="no GPU: turn two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of a bench run "
                          "made with --calib-copy-mib into profiles/traffic_<workload>.json")
     ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with the summary")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("PMC_DIR", "BENCH_JSON"),
+                    help="no GPU: turn one rocprofv3 --pmc pass (SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS, "
+                         "GRBM_GUI_ACTIVE) of a bench run into profiles/valu_<workload>.json")
     args = ap.parse_args()
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary, args.calib_copy_mib or 256, args.traffic_command)
+    if args.valu_summary:
+        return valu_summary(*args.valu_summary, args.traffic_command)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one server's share runs on one "
@@ -337,10 +385,59 @@ def main():
         return serve_bench(args, pir)
     if args.workload == "c3":
         return stream_bench(args, pir, torch)
-    w = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B, "c3b": configs.C3}[args.workload]
+    key = args.workload
+    w = WORKLOADS[key]
     B = args.B or w.B or 1024
-    full = (args.step or ("full" if w.fill == "cuckoo" else "read")) == "full"
-    K, W = args.steps, args.warmup
+    big = w.db_bytes > (1 << 30)
+    cpu_rows = args.cpu_rows or (16 if big else B)
+    cpu_single = args.cpu_rows_single if args.cpu_rows_single >= 0 else (2 if big else 16)
+    line = fixed_bench(args, pir, torch, w, B, args.steps, args.warmup, cpu_rows, cpu_single,
+                       latency=args.latency_reads)
+    if key == "c4a" and not args.no_extra and not (args.kind or args.prep or args.masked or args.B):
+        # the paper-scale 256 MiB database as a second, cache-sized case
+        sub = fixed_bench(args, pir, torch, configs.C2, configs.C2.B, 50, 5, 16, 0, latency=50)
+        line["extra"] = {"c2": {k: sub[k] for k in ("value", "ms_per_step", "config", "roofline", "cpu_baseline",
+                                                   "parity_sampled", "read_latency_ms")}}
+    print(json.dumps(line), flush=True)
+
+
+WORKLOADS = {"c1": configs.C1, "c2": configs.C2, "c4a": configs.C4A, "c4b": configs.C4B, "c3b": configs.C3}
+
+
+def host_info() -> dict:
+    """Host cores the CPU baseline may use: count, affinity mask and model."""
+    aff = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(os.cpu_count() or 1))
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    mask = 0
+    for c in aff:
+        mask |= 1 << c
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(aff), "affinity_mask": hex(mask), "cpu_model": model}
+
+
+def percentile(x, q: float) -> float:
+    """Nearest-rank percentile."""
+    x = np.sort(np.asarray(x, dtype=np.float64))
+    if x.size == 0:
+        return float("nan")
+    return float(x[min(x.size - 1, max(0, int(np.ceil(q / 100.0 * x.size)) - 1))])
+
+
+def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_rows_single: int, latency: int):
+    """One workload with a fixed batch size: K timed steps after W warm-up steps.
+
+    A step is the whole server path for one batch: ceil(B/10) writes (cuckoo
+    inserts with garbage collection for cuckoo-filled databases, whole-bucket
+    writes otherwise) with 6 interest bits each, the epoch commit that publishes
+    them, the read of the B request rows on the new snapshot, and the fetch of
+    the global interest vector."""
+    full = (args.step or "full") == "full"
     log(f"[bench] workload {w.name} n={w.n} d={w.d} z={w.z} B={B} step={'full' if full else 'read'}")
 
     # ---- database -------------------------------------------------------
@@ -465,9 +562,26 @@ def main():
     wall = time.perf_counter() - t0
     kern = db.profile_collect()
     db.profile_enable(False)
+    got = outs[(W + K - 1) % R].cpu().numpy()   # the last step's answers
+    got_iv = iv.cpu().numpy()
+    # Per-read latency: a read's answer is complete when its batch's is, so
+    # each of `latency` batches is issued alone on the published snapshot
+    # (requests already in device memory) and timed from the call to the
+    # completion of its answers.
+    lat = []
+    rs0 = read_streams[0]
+    for _ in range(latency):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        db.read_async(q, outs[0], stream=rs0)
+        rs0.synchronize()
+        lat.append(time.perf_counter() - t1)
+    lat_ms = {"p50": round(1e3 * percentile(lat, 50), 4), "p99": round(1e3 * percentile(lat, 99), 4),
+              "max": round(1e3 * max(lat), 4) if lat else None, "batches": len(lat), "reads_per_batch": B,
+              "what": "call to completed answers of a batch issued alone (device-resident requests)"}
     # The synchronous call (host request rows in, host answers out, so the
     # PCIe copies included), after the timed region: never the headline value.
-    n_sync = 10
+    n_sync = 10 if B <= 256 else 3
     db.read(req)
     t1 = time.perf_counter()
     for _ in range(n_sync):
@@ -488,8 +602,7 @@ def main():
                  "global_encode_ms": round(1e3 * t_enc, 3)}
     assert kern.size == min(-(-K // args.time_every), pir.PROFILE_MAX)
     kern_ms = float(np.mean(kern))
-    got = outs[(W + K - 1) % R].cpu().numpy()   # the last step's answers
-    got_iv = iv.cpu().numpy()
+    db.close()
 
     ms_per_step = 1000.0 * wall / K
     value = B * K / wall
@@ -503,10 +616,14 @@ def main():
     t_alu = xor_ops / (VALU_PEAK_TOPS * 1e12)
     if t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+                "unit": "TOP/s", "frac": round(alu_achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "achieved_is": "XORs of the plain method (one 32-bit XOR per selected bucket word) per second "
+                               "of the main read kernel"}
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "achieved_is": "algorithmic bytes (database once, requests, answers) per second of the main "
+                               "read kernel"}
     roof["traffic"] = measured_traffic(w.name, plan)
     lds = None if args.prep else lds_floor(plan, w.n, B, w.bucket_bytes)
     if lds:
@@ -516,12 +633,17 @@ def main():
     roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
                 hbm_frac=round(hbm_achieved / HBM_PEAK_GBS, 4), plain_xor_tops=round(alu_achieved, 3),
                 valu_frac=round(alu_achieved / VALU_PEAK_TOPS, 4), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
+    inst = measured_valu(w.name, plan)
+    if inst is not None:
+        # VALU instructions the kernel really executes (counter summary), as lane-operations per second
+        roof["valu_executed_frac"] = round(inst * 64 / t_kernel / (VALU_PEAK_TOPS * 1e12), 4)
 
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        hi = host_info()
+        threads = max(1, min(16, hi["affinity_cpus"]))
         # the oracle rebuilds the final snapshot from the same writes
         if ck is not None:
             ref = oracle.Cuckoo(w.n, w.d, w.z, capacity=w.cuckoo_items, seed=w.cuckoo_seed,
@@ -531,29 +653,41 @@ def main():
                 ref.insert_many(wr[0][:total_w], wr[1][:total_w], wr[2][:total_w], wr[3][:total_w])
             D = ref.table()
         else:
-            D = D0
+            D = D0                       # the device holds its own copy: apply the writes in place
             if full:
-                D = D0.copy()
                 for i in range(total_w):
                     D[int(wr[1][i])] = wr[3][i]
         # sampled rows spread over the batch (every block of a preprocessed read)
-        rows = np.unique(np.linspace(0, B - 1, min(args.cpu_rows, B)).round().astype(np.int64))
+        rows = np.unique(np.linspace(0, B - 1, min(cpu_rows, B)).round().astype(np.int64))
         t1 = time.perf_counter()
         want = (oracle.pir_read_masked(D, req[rows], seeds[rows], threads=threads) if args.masked
                 else oracle.pir_read(D, req[rows], threads=threads))
         dt = time.perf_counter() - t1
         parity = bool(np.array_equal(want, got[rows]))
+        single = None
+        if cpu_rows_single:
+            r1 = rows[:cpu_rows_single]
+            t1 = time.perf_counter()
+            want1 = oracle.pir_read(D, req[r1], threads=1)
+            dt1 = time.perf_counter() - t1
+            parity = parity and bool(np.array_equal(want1, got[r1]))
+            single = {"value": round(len(r1) / dt1, 3), "rows": int(len(r1)), "seconds": round(dt1, 3)}
         if full:
             last = W + K - 1
             epochs = [np.zeros(0, np.uint32)] + [ipos[k * nw:(k + 1) * nw].reshape(-1) for k in range(W + K)]
             want_iv = oracle.interest_window(IV_BITS, epochs, last + 1, IV_WINDOW)
             parity = parity and bool(np.array_equal(want_iv, got_iv))
-        cpu = {"value": round(len(rows) / dt, 2), "unit": "reads/s", "cores": threads, "kind": "oracle",
+        part = len(rows) < B
+        cpu = {"value": round(len(rows) / dt, 3), "unit": "reads/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(rows)} of the {B} request rows of the last batch over the full "
-                         f"{w.db_bytes >> 20} MiB snapshot, plain C byte loop (gcc -O2), {threads} threads"}
-        log(f"[bench] oracle {cpu['value']} reads/s on {threads} threads; parity={parity}")
+                         f"{w.db_bytes >> 20} MiB snapshot, plain C byte loop (gcc -O2), {threads} threads, "
+                         f"{dt:.2f} s" + ("; reads/s extrapolated from the sample" if part else ""),
+               "extrapolated": part, "single_thread": single, **hi}
+        log(f"[bench] oracle {cpu['value']} reads/s on {threads} threads"
+            + (f", {single['value']} on one" if single else "") + f"; parity={parity}")
+    del D0
 
-    line = {
+    return {
         "metric": "PIR bucket-reads/sec",
         "value": round(value, 1),
         "unit": "reads/s",
@@ -575,12 +709,11 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sampled": parity,
+        "read_latency_ms": lat_ms,
         "host_ms_per_step": {key: round(1e3 * v / K, 4) for key, v in host_s.items()},
         "interest_codec": codec,
         "pcie_inclusive": pcie,
     }
-    print(json.dumps(line), flush=True)
-    db.close()
 
 
 if __name__ == "__main__":

@@ -375,6 +375,9 @@ uint64_t pir_cuckoo_live(const pir_cuckoo *c);
  *   - A read arriving at time t is admitted once a memory slot is free (each
  *     in-flight read holds ceil(n/8) request bytes and one response bucket of
  *     device memory; mem_budget bounds the total). Admitted reads queue.
+ *     A mem_budget below one read's bytes (the request row at its pitch plus
+ *     one response row) could never admit a read: the call returns PIR_EBUSY
+ *     before serving anything.
  *   - Whenever one of `lanes` device lanes (each its own HIP stream and
  *     buffers) is free, up to max_batch queued reads leave as one batch: their
  *     request rows are gathered from pinned host memory by a kernel, answered

@@ -448,7 +448,7 @@ def serve(db: "PirDB", table: "Cuckoo | None", *, read_t, read_row, req_pool, wr
     res.read_epoch = _ptr(ep, ctypes.c_uint64)
     probe = np.zeros(0, np.uint64) if probe is None else np.ascontiguousarray(np.sort(probe), dtype=np.uint64)
     presp = np.zeros((probe.size, db.bucket_bytes), dtype=np.uint8)
-    piv = np.zeros((probe.size, (getattr(db, "m_bits", 1 << 20) + 7) // 8), dtype=np.uint8) if with_iv else None
+    piv = np.zeros((probe.size, (getattr(db, "m_bits", IV_DEFAULT_BITS) + 7) // 8), dtype=np.uint8) if with_iv else None
     res.n_probe = probe.size
     res.probe = _ptr(probe, ctypes.c_uint64)
     res.probe_resp = _ptr(presp)

@@ -1,8 +1,8 @@
 // Roofline probe for gfx950: the measured counterparts of the peaks the read
 // kernels are judged against.
 //   * HBM: a streaming read of a 4 GiB buffer (16 B per lane, coalesced).
-//   * VALU: 32-bit three-input bitwise operations (v_bitop3_b32), eight
-//     independent chains per lane.
+//   * VALU: 32-bit bitwise operations (v_bitop3_b32, v_xor_b32) in chains
+//     per lane, at several chain counts and waves per SIMD.
 //   * LDS: aggregate throughput of the access patterns the Four-Russians
 //     kernels use. Every lane of a wave touches consecutive bytes of one
 //     contiguous row slice (64 lanes x W dwords), so the accesses are free of
@@ -111,23 +111,58 @@ __global__ __launch_bounds__(256) void hbm_read(const uint4 *__restrict__ src, u
     out[blockIdx.x * 256 + threadIdx.x] = acc.x ^ acc.y ^ acc.z ^ acc.w;
 }
 
-// Eight dependent chains of three-input XORs per lane (each op counts once).
-__global__ __launch_bounds__(256) void valu_bitop3(uint32_t *out, int iters)
+// CH chains of 32-bit bitwise operations per lane, each step of a chain
+// depending on two other chains: three-input XORs (v_bitop3_b32) when OP3,
+// else two-input XORs (v_xor_b32). UNROLL steps of the iteration loop per
+// back-edge, so that the loop's scalar bookkeeping shrinks against the VALU
+// work. Every operation counts once.
+template <int CH, bool OP3, int UNROLL>
+__global__ __launch_bounds__(256) void valu_chain(uint32_t *out, int iters)
 {
-    uint32_t a[8];
+    uint32_t a[CH];
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < CH; ++k)
         a[k] = threadIdx.x * (k + 3) + blockIdx.x;
+#pragma unroll UNROLL
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            a[k] = __builtin_amdgcn_bitop3_b32(a[k], a[(k + 1) & 7], a[(k + 3) & 7], 0x96);
+        for (int k = 0; k < CH; ++k) {
+            if constexpr (OP3)
+                a[k] = __builtin_amdgcn_bitop3_b32(a[k], a[(k + 1) % CH], a[(k + 3) % CH], 0x96);
+            else
+                a[k] ^= a[(k + 1) % CH];
+        }
     }
     uint32_t r = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < CH; ++k)
         r ^= a[k];
     out[blockIdx.x * 256 + threadIdx.x] = r;
+}
+
+// Times one VALU variant at `blocks_per_cu` workgroups of 4 waves per CU (one
+// wave per SIMD each) and prints lane-operations per second and per CU clock.
+template <int CH, bool OP3, int UNROLL>
+int run_valu(const char *what, uint32_t *d, int cus, int blocks_per_cu)
+{
+    const int grid = cus * blocks_per_cu, iters = 20000;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return 1;
+    hipLaunchKernelGGL((valu_chain<CH, OP3, UNROLL>), dim3(grid), dim3(256), 0, 0, d, 16);
+    (void)hipEventRecord(a, 0);
+    hipLaunchKernelGGL((valu_chain<CH, OP3, UNROLL>), dim3(grid), dim3(256), 0, 0, d, iters);
+    (void)hipEventRecord(b, 0);
+    if (hipEventSynchronize(b) != hipSuccess)
+        return 1;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    const double ops = (double)grid * 256 * iters * CH;
+    printf("%-40s %2d waves/SIMD %7.2f T ops/s %6.1f lane-ops/clk/CU\n", what, blocks_per_cu, ops / ms / 1e9,
+           ops / (ms * 1e-3) / cus / 2.4e9);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return 0;
 }
 
 template <int MODE, int W>
@@ -189,22 +224,14 @@ int main()
         printf("%-40s %7.1f GB/s (4 GiB, 5 passes)\n", "HBM streaming read", 5.0 * bytes / ms / 1e6);
         (void)hipFree(src);
     }
-    {   // VALU
-        const int grid = cus * 8, iters = 20000;
-        hipEvent_t a, b;
-        (void)hipEventCreate(&a);
-        (void)hipEventCreate(&b);
-        hipLaunchKernelGGL(valu_bitop3, dim3(grid), dim3(256), 0, 0, d, 10);
-        (void)hipEventRecord(a, 0);
-        hipLaunchKernelGGL(valu_bitop3, dim3(grid), dim3(256), 0, 0, d, iters);
-        (void)hipEventRecord(b, 0);
-        if (hipEventSynchronize(b) != hipSuccess)
-            return 1;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        const double ops = (double)grid * 256 * iters * 8;
-        printf("%-40s %7.2f T ops/s\n", "v_bitop3_b32 (32-bit, per lane)", ops / ms / 1e9);
-    }
+    // VALU: the first line is the figure the read kernels are compared with
+    // (eight chains of three-input XORs, 8 waves per SIMD); the others vary
+    // the operation, the chains per lane and the waves per SIMD.
+    rc |= run_valu<8, true, 1>("v_bitop3_b32, 8 chains", d, cus, 8);
+    rc |= run_valu<16, true, 4>("v_bitop3_b32, 16 chains, unroll 4", d, cus, 8);
+    rc |= run_valu<16, false, 4>("v_xor_b32, 16 chains, unroll 4", d, cus, 8);
+    for (int w : {1, 2, 4})
+        rc |= run_valu<16, true, 4>("v_bitop3_b32, 16 chains, unroll 4", d, cus, w);
     rc |= run<0, 1>("ds_read_b32 (4 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 2>("ds_read_b64 (8 B per lane)", d, p.multiProcessorCount);
     rc |= run<0, 4>("ds_read_b128 (16 B per lane)", d, p.multiProcessorCount);

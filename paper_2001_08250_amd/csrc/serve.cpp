@@ -124,9 +124,12 @@ extern "C" int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_conf
     const uint64_t qb = db->qbytes, qp = db->qpitch, bb = db->bucket_bytes;
     const uint64_t iv_bytes = (db->m_bits + 7) / 8;
     const uint32_t MB = cfg->max_batch;
+    // a budget below one read's device bytes could never admit a read
+    if (cfg->mem_budget && cfg->mem_budget < qp + db->stride)
+        return PIR_EBUSY;
     uint64_t slots = (uint64_t)cfg->lanes * MB;
     if (cfg->mem_budget)
-        slots = std::max<uint64_t>(1, cfg->mem_budget / (qp + db->stride));
+        slots = cfg->mem_budget / (qp + db->stride);
 
     Resources R;
     int rc = host_alloc(&R.pool, tr->pool_rows * qp);

@@ -75,7 +75,7 @@ def test_serving_matches_oracle_per_epoch(max_batch, lanes, prep):
         assert (out["latency_s"] > 0).all()
         ep = out["read_epoch"]
         wep = out["write_epoch"]
-        last = int(max(ep.max(), e0))
+        last = int(max(ep.max(), e0, db.epoch))
         snaps = _oracle_snapshots(pre, writes, wep, e0, last)
         # interest deltas per epoch (epoch e's delta holds the writes published by commit e)
         deltas = [np.zeros(0, np.uint32) for _ in range(last + 1)]
@@ -87,11 +87,17 @@ def test_serving_matches_oracle_per_epoch(max_batch, lanes, prep):
             assert_rows_equal(out["probe_resp"][k][None, :], want, f"read {rd} epoch {e}")
             iv = oracle.interest_window(M_BITS, deltas[1:e + 1], e - 1, WINDOW)
             assert np.array_equal(out["probe_iv"][k], iv), f"interest vector of read {rd} (epoch {e})"
-        # alone (B = 1) on the final snapshot equals the oracle on it too
-        final = snaps[last] if db.epoch == last else None
-        if final is not None:
-            for r in range(0, 64, 9):
-                assert_rows_equal(db.read(pool[r][None, :]), oracle.pir_read(final, pool[r][None, :]), "alone")
+        # alone (B = 1) on the published snapshot equals the oracle on it too,
+        # and the probed reads that the mix answered from that snapshot give
+        # the same bytes when asked again alone
+        final = snaps[db.epoch]
+        for r in range(0, 64, 9):
+            assert_rows_equal(db.read(pool[r][None, :]), oracle.pir_read(final, pool[r][None, :]), "alone")
+        again = [k for k, rd in enumerate(out["probe"]) if ep[rd] == db.epoch][:16]
+        for k in again:
+            rd = out["probe"][k]
+            assert_rows_equal(db.read(pool[rows[rd]][None, :]), out["probe_resp"][k][None, :],
+                              f"read {rd} alone vs in the mix")
 
 
 def test_serving_rejects_bad_config():
@@ -102,3 +108,50 @@ def test_serving_rejects_bad_config():
         with pytest.raises(pir.PirError) as e:
             pir.serve(db, None, read_t=[0.0], read_row=[9], req_pool=pool)
         assert e.value.code == pir.PIR_ERANGE
+
+
+def test_serving_default_interest_vector_rows():
+    """with_iv=True on a handle that kept the library's default interest
+    configuration: every probed read returns the whole default-sized vector."""
+    n = 256
+    pre = synth.write_ops(711, 300, n, 64)
+    read_t = synth.poisson_arrivals(712, 400, 0.2)
+    write_t = synth.poisson_arrivals(714, 40, 0.2)
+    pool = synth.bernoulli_requests(713, 8, n)
+    rows = np.random.default_rng(715).integers(0, 8, size=read_t.size).astype(np.uint32)
+    writes = synth.write_ops(716, write_t.size, n, 64)
+    interest = synth.interest_positions(717, write_t.size, K, pir.IV_DEFAULT_BITS)
+    with pir.PirDB(n, 2, 64) as db:
+        table = pir.Cuckoo(db, capacity=600, seed=5)
+        table.insert_many(*pre)
+        table.stage()
+        db.commit()
+        probe = np.arange(read_t.size)
+        out = pir.serve(db, table, read_t=read_t, read_row=rows, req_pool=pool, write_t=write_t, writes=writes,
+                        write_interest=interest, max_batch=16, lanes=2, epoch_s=0.05, probe=probe, with_iv=True)
+        assert out["probe_iv"].shape == (read_t.size, pir.IV_DEFAULT_BITS // 8)
+        ep = out["read_epoch"]
+        wep = out["write_epoch"]
+        e_first = int(ep.min())
+        deltas = [np.zeros(0, np.uint32) for _ in range(int(ep.max()) + 1)]
+        for e in range(1, int(ep.max()) + 1):
+            deltas[e] = interest[wep == e].reshape(-1)
+        for k, rd in enumerate(probe):
+            e = int(ep[rd])
+            want = oracle.interest_window(pir.IV_DEFAULT_BITS, deltas[1:e + 1], e - 1, pir.IV_DEFAULT_WINDOW)
+            assert np.array_equal(out["probe_iv"][k], want), f"read {rd} epoch {e} (first {e_first})"
+
+
+def test_serving_budget_below_one_read_is_busy():
+    """A memory budget that cannot hold one read (its request row and one
+    response row) can never admit a read: PIR_EBUSY, nothing served."""
+    n = 1024
+    with pir.PirDB(n, 4, 256) as db:
+        pool = synth.bernoulli_requests(3, 4, n)
+        with pytest.raises(pir.PirError) as e:
+            pir.serve(db, None, read_t=[0.0, 0.001], read_row=[0, 1], req_pool=pool, max_batch=4,
+                      mem_budget=n // 8 + 4 * 256 - 1)
+        assert e.value.code == pir.PIR_EBUSY
+        out = pir.serve(db, None, read_t=[0.0, 0.001], read_row=[0, 1], req_pool=pool, max_batch=4,
+                        mem_budget=n // 8 + 4 * 256)
+        assert out["completed"] == 2
