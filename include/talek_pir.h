@@ -129,6 +129,29 @@ int pir_read_batch_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint
                          void *d_resp, uint64_t resp_pitch, void *hip_stream);
 
 /*
+ * Allocation-free variant of pir_read_batch_async, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, the same answers,
+ * and no allocation of any kind inside the call. Its device scratch (split
+ * partial answers, Four-Russians request offsets, restaged rows) lies in one
+ * static device array of PIR_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; the read takes the handle's schedule with its bucket splits
+ * reduced (or the masked kernel) until that scratch fits. Preprocessed
+ * (Strassen) leaves are not used.
+ *   PIR_ERANGE: restaging the rows alone needs more than the array (only
+ *     reachable with unaligned rows: B * round_up(ceil(n/8), 16) plus
+ *     B * round_up(d * msg_bytes, 16) above PIR_NOALLOC_SCRATCH_BYTES).
+ *   PIR_EINVAL: as pir_read_batch_async.
+ * Every call on one GPU shares that GPU's array and the handle's reader
+ * event of the snapshot copy: calls whose device work overlaps (on any
+ * handles or streams of the same GPU) race and give undefined answers; order
+ * them on one stream or wait between them.
+ */
+#define PIR_NOALLOC_SCRATCH_BYTES (32ull << 20)
+int pir_read_batch_noalloc_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_t B,
+                                 void *d_resp, uint64_t resp_pitch, void *hip_stream);
+
+/*
  * Uneven batch stream: n_batches batches, batch k holding sizes[k] request
  * rows. Batch k reads request rows req_first[k] .. req_first[k] + sizes[k] - 1
  * of d_req and writes response rows resp_first[k] .. of d_resp (row indices,

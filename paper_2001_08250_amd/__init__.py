@@ -96,6 +96,7 @@ SIGNATURES = {
     "pir_epoch": (_u64, [_vp]),
     "pir_read_batch": (ctypes.c_int, [_vp, _u8p, _u32, _u8p]),
     "pir_read_batch_async": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp, _u64, _vp]),
+    "pir_read_batch_noalloc_async": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp, _u64, _vp]),
     "pir_read_stream_async": (ctypes.c_int, [_vp, _vp, _u64, _u32p, _u64p, _u32, _vp, _u64, _u64p, _vp]),
     "pir_read_batch_masked": (ctypes.c_int, [_vp, _u8p, _u32, _u8p, _u8p]),
     "pir_read_batch_masked_async": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp, _vp, _u64, _vp]),

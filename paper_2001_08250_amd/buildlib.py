@@ -28,6 +28,7 @@ SOURCES = [
     "mask.hip",
     "iv_codec.hip",
     "strassen.hip",
+    "noalloc.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value", f"-I{os.path.join(ROOT, 'include')}"]

@@ -86,6 +86,9 @@ struct pir_db {
     bool all_dirty = false;
 
     std::unordered_map<hipStream_t, talek::Scratch> scratch;
+    // Its address keys the allocation-free reads' reader events in
+    // readers[0] and readers[1] (created with the handle; never a stream).
+    char noalloc_key = 0;
     talek::Plan forced{0, 0, 0, 0, 0};
 
     // interest vector
@@ -135,6 +138,12 @@ Plan choose_plan(pir_db *db, uint32_t B);
 ReadGeom read_geom(pir_db *db, const void *q, uint64_t qpitch, uint32_t B, void *out, uint64_t out_pitch);
 // Scratch of a stream (created on first use).
 Scratch &scratch_for(pir_db *db, hipStream_t s);
+// Order `s` after the latest publication.
+int wait_published(pir_db *db, hipStream_t s);
+// Device address of the allocation-free reads' static scratch on `device`
+// (the current device), taken once per device.
+int noalloc_setup(int device);
+inline hipStream_t noalloc_reader_key(pir_db *db) { return reinterpret_cast<hipStream_t>(&db->noalloc_key); }
 // Compressed stream of the m-bit device vector `words` into host memory (out
 // may be NULL: size only); stream-ordered on s, returns when done.
 int encode_interest(pir_db *db, const uint32_t *words, uint64_t m, uint8_t *out, uint64_t cap, uint64_t *out_bytes,

@@ -369,6 +369,20 @@ int pir_db_create(uint64_t n, uint32_t d, uint32_t msg_bytes, pir_db **out)
                 rc = PIR_EDEVICE;
         if (rc != PIR_OK)
             break;
+        // allocation-free reads: the static scratch of this device and one
+        // reader event per snapshot copy, made here so that those reads
+        // create nothing
+        if ((rc = talek::noalloc_setup(db->device)) != PIR_OK)
+            break;
+        for (int b = 0; b < 2 && rc == PIR_OK; ++b) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreate(&ev) != hipSuccess)
+                rc = PIR_EDEVICE;
+            else
+                db->readers[b].emplace(talek::noalloc_reader_key(db), ev);
+        }
+        if (rc != PIR_OK)
+            break;
         void *p = nullptr;
         db->rows_alloc = talek::padded_db_rows(n);
         if (hipMalloc(&p, db->rows_alloc * stride) != hipSuccess) { rc = PIR_ENOMEM; break; }
