@@ -183,6 +183,13 @@ class Cuckoo:
         buf = (ctypes.c_uint8 * (self.n * self.d * self.z)).from_address(p)
         return np.frombuffer(buf, dtype=np.uint8).reshape(self.n, self.d * self.z).copy()
 
+    def table_view(self) -> np.ndarray:
+        """The table bytes as uint8 [n, d * z] without a copy: valid until the
+        next insert or close (for reading large tables between inserts)."""
+        p = self._lib.oracle_cuckoo_table(self._h)
+        buf = (ctypes.c_uint8 * (self.n * self.d * self.z)).from_address(p)
+        return np.frombuffer(buf, dtype=np.uint8).reshape(self.n, self.d * self.z)
+
     def live(self) -> int:
         return int(self._lib.oracle_cuckoo_live(self._h))
 

@@ -48,10 +48,31 @@ C4B = Workload("xorpir-n1M-d2-z4k-B2048", n=1 << 20, d=2, z=4 * KiB, B=2048, db_
 C5 = Workload("serve-n1M-d4-z1k", n=1 << 20, d=4, z=1 * KiB, fill="cuckoo", cuckoo_items=3_145_728,
               cuckoo_seed=3005, req_seed=2005,
               extra={"arrival_seed": 4005, "rates": (5_000, 20_000, 50_000), "write_frac": 0.1,
-                     "interest_bits": 1 << 17, "interest_k": 6, "window": 100, "epoch_s": 1.0})
+                     "interest_bits": 1 << 20, "interest_k": 6, "window": 100, "epoch_s": 1.0})
 
 ALL = {w.name: w for w in (C1, C2, C3, C4A, C4B, C5)}
 BY_KEY = {"c1": C1, "c2": C2, "c3": C3, "c4a": C4A, "c4b": C4B, "c5": C5}
 
 # Blocked cuckoo parameters shared by every cuckoo-filled workload.
 CUCKOO_MAX_KICKS = 500
+
+
+# GetUpdates sizing (section "Evaluation", cost of operations: the interest
+# vector grows linearly with the number n of stored messages so as to keep a
+# false-positive rate of 0.02 over a TTL of 100 write intervals). Reading: a
+# GetUpdates transfers one compressed delta, the messages of one write
+# interval (n / TTL of them); each message sets one position (one hash, the
+# compressed-Bloom-filter choice that minimises what is sent) in a vector of
+# m = ceil(n / ln(1 / (1 - 0.02))) bits, so that the global vector over the
+# TTL window of deltas (all n messages) has false-positive rate 0.02.
+GETUPDATES_FP = 0.02
+GETUPDATES_TTL = 100
+GETUPDATES_MESSAGES = (10_000, 100_000, 1_000_000)
+# the paper's GetUpdates row (KB) at those message counts
+GETUPDATES_PAPER_KB = {10_000: 0.21, 100_000: 1.40, 1_000_000: 14.00}
+
+
+def getupdates_shape(n_messages: int, fp: float = GETUPDATES_FP, ttl: int = GETUPDATES_TTL) -> dict:
+    import math
+    return {"m_bits": math.ceil(n_messages / -math.log1p(-fp)), "k": 1,
+            "per_interval": n_messages // ttl, "window": ttl}
