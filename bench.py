@@ -196,46 +196,115 @@ def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
 
 
 def serve_bench(args, pir):
-    """Serving workload: open-loop Poisson reads with 10% writes published every epoch."""
-    import torch  # noqa: F401  (device already selected by the caller)
+    """Serving workload: open-loop Poisson reads with 10% writes published every
+    epoch, each read returning its answer and the global interest vector.
+
+    Per arrival rate: `warmup_s` + `duration` seconds of arrivals served by the
+    continuous-batching loop (latency and throughput over the reads that arrive
+    after the warm-up), then the one-launch-per-read baseline on the first
+    `baseline_s` seconds of the same trace. Probed reads (64 per rate, spread
+    over the run) are checked against the oracle's cuckoo replay on the
+    snapshot of the epoch that answered them, and their interest vectors
+    against the oracle's window over the published deltas."""
+    import oracle
     w = configs.C5
     x = w.extra
-    dur = args.duration
+    iv_bits = args.iv_bits or x["interest_bits"]
+    dur, warm = args.duration, args.warmup_s
     t = time.perf_counter()
     db = pir.PirDB(w.n, w.d, w.z)
-    db.interest_config(x["interest_bits"], x["window"])
+    db.interest_config(iv_bits, x["window"])
     pre = synth.write_ops(w.cuckoo_seed, w.cuckoo_items, w.n, w.z)
     ck = pir.Cuckoo(db, capacity=w.cuckoo_items, seed=w.cuckoo_seed, max_kicks=configs.CUCKOO_MAX_KICKS)
     ck.insert_many(*pre)
     ck.stage()
-    db.commit()
+    e_pre = db.commit()
+    ref = None
+    if not args.no_parity:
+        ref = oracle.Cuckoo(w.n, w.d, w.z, capacity=w.cuckoo_items, seed=w.cuckoo_seed,
+                            max_kicks=configs.CUCKOO_MAX_KICKS)
+        ref.insert_many(*pre)
     del pre
     log(f"[serve] {w.name}: database of {w.db_bytes >> 30} GiB ready in {time.perf_counter() - t:.1f}s")
     pool = synth.bernoulli_requests(w.req_seed, 1024, w.n)
+    deltas = {}        # published epoch -> interest positions of the writes it published
     results = []
+    parity_all = None if ref is None else True
+    checked = 0
+
+    def publish_rest(writes, wep, ipos):
+        """Publish what the run left staged; feed the run's writes to the oracle in order."""
+        e_end = db.commit()
+        wep = wep.copy()
+        wep[wep == np.iinfo(np.uint64).max] = e_end
+        for e in np.unique(wep):
+            deltas.setdefault(int(e), []).append(ipos[wep == e].reshape(-1))
+        return wep
+
     for rate in [r for r in x["rates"] if not args.rates or r in args.rates]:
-        read_t = synth.poisson_arrivals(x["arrival_seed"] + rate, rate, dur)
+        span = warm + dur
+        read_t = synth.poisson_arrivals(x["arrival_seed"] + rate, rate, span)
         rows = synth.uniform_indices(x["arrival_seed"] + rate + 1, read_t.size, 1024).astype(np.uint32)
-        write_t = synth.poisson_arrivals(x["arrival_seed"] + rate + 2, x["write_frac"] * rate, dur)
+        write_t = synth.poisson_arrivals(x["arrival_seed"] + rate + 2, x["write_frac"] * rate, span)
         writes = synth.write_ops(w.cuckoo_seed + rate, write_t.size, w.n, w.z,
                                  id_offset_seed=w.cuckoo_seed + rate + 3)
-        ipos = synth.interest_positions(x["arrival_seed"] + rate + 4, write_t.size, x["interest_k"],
-                                        x["interest_bits"])
+        ipos = synth.interest_positions(x["arrival_seed"] + rate + 4, write_t.size, x["interest_k"], iv_bits)
         row = {"rate": rate, "reads": int(read_t.size), "writes": int(write_t.size)}
         for mode, mb, lanes in (("batched", args.max_batch, args.lanes), ("one_per_read", 1, 4)):
             if mode == "one_per_read" and args.no_baseline:
                 continue
             # the one-launch-per-read baseline is given a shorter slice of the same trace
-            n_r = read_t.size if mode == "batched" else int(np.searchsorted(read_t, min(dur, args.baseline_s)))
+            n_r = read_t.size if mode == "batched" else int(np.searchsorted(read_t, min(span, args.baseline_s)))
             n_w = int(np.searchsorted(write_t, read_t[n_r - 1])) if n_r else 0
+            post = np.nonzero(read_t[:n_r] >= (warm if mode == "batched" else 0.0))[0]
+            probe = None
+            if mode == "batched" and ref is not None and post.size:
+                probe = post[np.unique(np.linspace(0, post.size - 1, args.probes).round().astype(np.int64))]
             log(f"[serve] rate {rate}/s {mode}: {n_r} reads, {n_w} writes")
+            wsl = tuple(a[:n_w] for a in writes)
             out = pir.serve(db, ck, read_t=read_t[:n_r], read_row=rows[:n_r], req_pool=pool,
-                            write_t=write_t[:n_w], writes=tuple(a[:n_w] for a in writes),
-                            write_interest=ipos[:n_w], max_batch=mb, lanes=lanes, epoch_s=x["epoch_s"])
-            row[mode] = {"reads_per_s": round(out["reads_per_s"], 1), "p50_ms": round(1e3 * out["p50_s"], 3),
-                         "p99_ms": round(1e3 * out["p99_s"], 3), "max_ms": round(1e3 * out["max_s"], 3),
-                         "mean_batch": round(out["mean_batch"], 1), "batches": int(out["batches"]),
-                         "epochs": int(out["epochs"]), "wall_s": round(out["wall_s"], 3)}
+                            write_t=write_t[:n_w], writes=wsl, write_interest=ipos[:n_w], max_batch=mb,
+                            lanes=lanes, epoch_s=x["epoch_s"], probe=probe, with_iv=probe is not None)
+            lat = out["latency_s"][post]
+            done_t = read_t[post] + lat
+            t0 = warm if mode == "batched" else 0.0
+            served = post.size / max(float(done_t.max()) - t0, 1e-9) if post.size else 0.0
+            row[mode] = {"reads_per_s": round(served, 1), "p50_ms": round(1e3 * percentile(lat, 50), 3),
+                         "p99_ms": round(1e3 * percentile(lat, 99), 3), "max_ms": round(1e3 * float(lat.max()), 3),
+                         "measured_reads": int(post.size), "mean_batch": round(out["mean_batch"], 1),
+                         "batches": int(out["batches"]), "epochs": int(out["epochs"]),
+                         "wall_s": round(out["wall_s"], 3)}
+            wep = publish_rest(wsl, out["write_epoch"], ipos[:n_w])
+            if ref is not None:
+                # the oracle replays the run's writes epoch by epoch and answers
+                # each probed read on the snapshot of the epoch that served it
+                ep = out["read_epoch"]
+                need = {} if probe is None else {int(e): [] for e in ep[probe]}
+                for k, rd in enumerate(probe if probe is not None else []):
+                    need[int(ep[rd])].append(k)
+                ok = True
+                order = np.argsort(wep, kind="stable")
+                pos = 0
+                for e in sorted(set(int(v) for v in np.unique(wep)) | set(need)):
+                    sel = []
+                    while pos < order.size and int(wep[order[pos]]) <= e:
+                        sel.append(order[pos])
+                        pos += 1
+                    if sel:
+                        sel = np.sort(np.asarray(sel))
+                        ref.insert_many(wsl[0][sel], wsl[1][sel], wsl[2][sel], wsl[3][sel])
+                    if e in need:
+                        ks = need[e]
+                        rds = probe[ks]
+                        want = oracle.pir_read(ref.table_view(), pool[rows[rds]], threads=16)
+                        ok = ok and bool(np.array_equal(want, out["probe_resp"][ks]))
+                        ev = [np.concatenate(deltas.get(i, [np.zeros(0, np.uint32)])) for i in range(1, e + 1)]
+                        want_iv = oracle.interest_window(iv_bits, ev, e - 1, x["window"])
+                        ok = ok and all(np.array_equal(want_iv, out["probe_iv"][k]) for k in ks)
+                        checked += len(ks)
+                if probe is not None:
+                    row[mode]["parity"] = {"probed_reads": int(probe.size), "epochs": len(need), "bit_exact": ok}
+                parity_all = parity_all and ok
             log(f"[serve]   {row[mode]}")
         results.append(row)
     db.close()
@@ -253,15 +322,25 @@ def serve_bench(args, pir):
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z,
-                   "duration_s": dur, "max_batch": args.max_batch, "parallelism": "single-gpu"},
+        "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "duration_s": dur,
+                   "warmup_s": warm, "interest_bits": iv_bits, "interest_window": x["window"],
+                   "max_batch": args.max_batch, "lanes": args.lanes, "parallelism": "single-gpu"},
+        "p99_ms_at_best": best["batched"]["p99_ms"],
+        "parity": parity_all,
+        "parity_reads_checked": checked,
         "serving": results,
     }
     print(json.dumps(line), flush=True)
 
 
 def stream_bench(args, pir, torch):
-    """Uneven batches: n = 2^20 x 4 KiB, batch sizes uniform in [1, 1024]."""
+    """Uneven batches: n = 2^20 x 4 KiB, batch sizes uniform in [1, 1024].
+
+    Four ways to answer the same stream, each timed over `steps` passes after
+    one untimed pass: the fused launch groups of 1024 requests replayed from a
+    HIP graph, and one launch sequence per batch, each first with the
+    heuristic schedules and then with schedules that the tuner picked for
+    every batch-size class the stream uses."""
     w = configs.C3
     nb = args.batches or w.batches
     sizes = synth.batch_sizes(w.batch_seed, nb)
@@ -270,7 +349,6 @@ def stream_bench(args, pir, torch):
     D = synth.uniform_db(w.db_seed, w.n, w.bucket_bytes, threads=16)
     db = pir.PirDB(w.n, w.d, w.z)
     db.load(D)
-    del D
     pool = synth.bernoulli_requests(w.req_seed, 1024, w.n)
     rng = np.random.default_rng(w.batch_seed)
     first = np.array([rng.integers(0, 1024 - s + 1) for s in sizes], dtype=np.uint64)
@@ -279,43 +357,62 @@ def stream_bench(args, pir, torch):
     q = torch.from_numpy(pool).to(dev)
     out = torch.empty((total, w.bucket_bytes), dtype=torch.uint8, device=dev)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    res = {}
-    # (a) batches fused into launch groups of >= 256 requests, graph captured on
-    #     the first call and replayed
-    db.read_stream_async(q, sizes, out, req_first=first)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+
+    def fused():
         db.read_stream_async(q, sizes, out, req_first=first)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    res["fused_graph"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
-    # (b) one launch sequence per batch with the planner's schedule for its size
-    if args.tune:
-        for Bt in (1, 4, 16, 64, 256, 1024):
-            p, us = db.tune(Bt, iters=2)
-            log(f"[stream] tuned B={Bt}: {p} {us:.0f} us")
+
     def per_batch():
         for k in range(nb):
             b = int(sizes[k])
             f = int(first[k])
             db.read_async(q[f:f + b], out[starts[k]:starts[k] + b])
-    per_batch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        per_batch()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    res["per_batch_launch"] = {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
-    log(f"[stream] {res}")
-    best = max(res.values(), key=lambda r: r["reads_per_s"])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        return {"reads_per_s": round(total / dt, 1), "ms_per_stream": round(1e3 * dt, 2)}
+
+    res = {}
+    res["fused_graph_heuristic"] = timed(fused)
+    res["per_batch_heuristic"] = timed(per_batch)
+    if not args.no_tune:
+        # every batch-size class (next power of two) that either form launches:
+        # the fused groups (1024 requests, plus the last group's rest) and the
+        # batches themselves
+        rest = total % 1024
+        classes = sorted({1 << int(np.ceil(np.log2(max(int(b), 1)))) for b in list(sizes) + [1024, rest or 1024]})
+        t1 = time.perf_counter()
+        tuned = {}
+        for Bt in classes:
+            p, us = db.tune(Bt, iters=2)
+            tuned[Bt] = {"kind": p.kind, "tile": p.tile, "splits": p.splits, "unroll": p.unroll, "flags": p.flags,
+                         "us": round(us, 1)}
+            log(f"[stream] tuned B={Bt}: {p} {us:.0f} us")
+        res["tuning_s"] = round(time.perf_counter() - t1, 1)
+        res["tuned_plans"] = tuned
+        res["fused_graph_tuned"] = timed(fused)
+        res["per_batch_tuned"] = timed(per_batch)
+    # sampled answers against the oracle (rows spread over the stream)
+    import oracle
+    rows = np.unique(np.linspace(0, total - 1, 16).round().astype(np.int64))
+    k_of = np.searchsorted(starts, rows, side="right") - 1
+    req_rows = pool[first[k_of].astype(np.int64) + (rows - starts[k_of])]
+    want = oracle.pir_read(D, req_rows, threads=16)
+    parity = bool(np.array_equal(want, out.cpu().numpy()[rows]))
+    log(f"[stream] {res}; parity={parity}")
+    rates = {k: v for k, v in res.items() if isinstance(v, dict) and "reads_per_s" in v}
+    best = max(rates.values(), key=lambda r: r["reads_per_s"])
     line = {"metric": "PIR bucket-reads/sec (uneven batch stream)", "value": best["reads_per_s"], "unit": "reads/s",
             "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": best["ms_per_stream"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
             "config": {"workload": w.name, "n_buckets": w.n, "d": w.d, "msg_bytes": w.z, "batches": nb,
                        "reads": total, "parallelism": "single-gpu"},
-            "stream": res}
+            "stream": res, "parity_sampled": parity}
     print(json.dumps(line), flush=True)
     db.close()
 
@@ -326,7 +423,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4a", choices=["c1", "c2", "c3", "c4a", "c4b", "c3b", "c5"])
-    ap.add_argument("--duration", type=float, default=3.0, help="serving: seconds of arrivals per rate")
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: measured seconds of arrivals per rate")
+    ap.add_argument("--warmup-s", type=float, default=3.0, help="serving: seconds of arrivals before the measured ones")
+    ap.add_argument("--iv-bits", type=int, default=0, help="serving: interest-vector bits (default 2^20)")
+    ap.add_argument("--probes", type=int, default=64, help="serving: reads per rate checked against the oracle")
+    ap.add_argument("--no-parity", action="store_true", help="serving: skip the oracle replay")
     ap.add_argument("--baseline-s", type=float, default=1.0, help="serving: seconds of the one-per-read baseline")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: reads per launch (256: one request tile of the paired-table kernel)")
     ap.add_argument("--rates", type=int, nargs="*", default=[], help="serving: subset of the arrival rates")
@@ -342,6 +443,7 @@ def main():
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0, help="plan flags (1 = waves share a column chunk)")
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="uneven stream: skip the tuned schedules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")

@@ -73,3 +73,28 @@ def test_dense_and_full_vectors():
             assert s == oracle.iv_encode(np.full((m + 7) // 8, 0xFF, dtype=np.uint8), m)
             m2, v = oracle.iv_decode(s)
             assert m2 == m and np.unpackbits(v, bitorder="little")[:m].all()
+
+
+@pytest.mark.parametrize("n_msg", [10_000, 100_000, 1_000_000])
+def test_getupdates_payloads_at_the_papers_store_sizes(n_msg):
+    """The paper's GetUpdates sizing (false-positive rate 0.02 over a TTL of
+    100 write intervals, one position per message): after a full window of
+    write intervals the device encodes the global vector and the last delta
+    byte for byte as the oracle does."""
+    from synth import configs
+    sh = configs.getupdates_shape(n_msg)
+    m, per, win = sh["m_bits"], sh["per_interval"], sh["window"]
+    epochs = [synth.interest_positions(9000 + i, per, sh["k"], m).reshape(-1) for i in range(win)]
+    with pir.PirDB(64, 2, 32) as db:
+        db.interest_config(m, win)
+        for pos in epochs:
+            db.interest_add(pos)
+            db.commit()
+        last = pir.lib().pir_epoch(db.h)
+        glob = oracle.interest_window(m, epochs, win - 1, win)
+        want_g = oracle.iv_encode(glob, m)
+        want_d = oracle.iv_encode(oracle.interest_window(m, epochs[-1:], 0, 1), m)
+        got_g, got_d = db.interest_encoded(), db.interest_encoded(last)
+        say(f"n={n_msg}: m={m} delta {len(got_d)} B, global {len(got_g)} B")
+        assert got_g == want_g
+        assert got_d == want_d

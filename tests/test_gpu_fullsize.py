@@ -3,8 +3,8 @@
 * n = 65,536 x 4 KiB, cuckoo-filled with 200,000 messages, B = 256: the
   library's cuckoo table must equal the oracle's byte for byte, and every one
   of the 256 answers must equal the oracle's.
-* n = 2^20 x 4 KiB (4 GiB) uneven batch stream through the persistent
-  queue kernel; n = 2^22 x 4 KiB (16 GiB) and n = 2^20 x 8 KiB (8 GiB) with
+* n = 2^20 x 4 KiB (4 GiB) uneven batch stream through the fused launch
+  groups replayed from a HIP graph; n = 2^22 x 4 KiB (16 GiB) and n = 2^20 x 8 KiB (8 GiB) with
   B = 2048: seeded sampled rows against the oracle (each oracle row scans the
   whole database on the CPU).
 Every kernel family is run at the full size too (sampled rows).
