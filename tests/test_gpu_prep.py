@@ -122,3 +122,19 @@ def test_stream_and_commits_with_preprocessing_on():
                 assert_rows_equal(got[row:row + s], want, f"rep {rep} batch {k} (B={s})")
                 row += s
             assert_rows_equal(db.read(pool[:300]), oracle.pir_read(D, pool[:300]), f"rep {rep} leaves")
+
+
+@pytest.mark.parametrize("levels,n,d,z", [(1, 300, 1, 8192), (1, 300, 1, 16384), (2, 300, 1, 16384),
+                                          (1, 301, 1, 96), (2, 77, 3, 64)])
+def test_leaf_database_shapes(levels, n, d, z):
+    """Leaf databases whose blocks are as wide as a workgroup of 16-byte
+    columns or wider (one row per block, or several columns per thread), and
+    blocks of a few columns that do not divide the workgroup: every answer
+    bit-exact against the oracle."""
+    D = synth.uniform_db(900 + n + z, n, d * z)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=1)
+        for B in (2, 33):
+            req = synth.bernoulli_requests(950 + B + z, B, n)
+            assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"L={levels} n={n} bucket={d * z} B={B}")
