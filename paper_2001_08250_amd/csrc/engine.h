@@ -166,6 +166,10 @@ bool prep_tables(uint32_t levels, PrepTables *t);
 // blocks, rows Nq per block (rows >= n of D read as zero).
 hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, uint64_t n, uint64_t Nq, uint32_t Cq,
                          void *out, uint64_t leaf_bytes, hipStream_t stream);
+// The leaf rows x = idx[k] mod Nq (k < count, idx device-readable) of every
+// leaf, recomputed from D as launch_prep_d forms them.
+hipError_t launch_prep_rows(const PrepTables &t, const void *D, uint64_t stride, uint64_t n, uint64_t Nq, uint32_t Cq,
+                            const uint64_t *idx, uint64_t count, void *out, uint64_t leaf_bytes, hipStream_t stream);
 // Leaf requests: leaf i (leaf_bytes apart, rows out_pitch bytes, Bq rows of
 // Wq words) = XOR of its A blocks of the B request rows (bits >= n zero).
 hipError_t launch_prep_q(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n, uint32_t Bq,

@@ -477,11 +477,40 @@ int pir_db_write_range(pir_db *db, uint64_t first, uint64_t count, const uint8_t
     return PIR_OK;
 }
 
+// The epoch's dirty bucket indices in mapped pinned memory (device address
+// in *dev), for the kernels of the commit that read them in place; the
+// caller records UP_MIRROR after the last of them.
+static int upload_dirty(pir_db *db, const uint64_t **dev)
+{
+    const uint64_t cnt = db->dirty.size();
+    PIR_TRY(wait_upload(db, UP_MIRROR));
+    if (cnt > db->mirror_idx_cap) {
+        if (db->mirror_idx_host)
+            hipHostFree(db->mirror_idx_host);
+        db->mirror_idx_host = nullptr;
+        db->mirror_idx_cap = 0;
+        void *p = nullptr;
+        PIR_TRY(host_mapped(cnt * sizeof(uint64_t), &p, &db->mirror_map));
+        db->mirror_idx_host = static_cast<uint64_t *>(p);
+        db->mirror_idx_cap = cnt;
+    }
+    memcpy(db->mirror_idx_host, db->dirty.data(), cnt * sizeof(uint64_t));
+    *dev = static_cast<const uint64_t *>(db->mirror_map);
+    return PIR_OK;
+}
+
 // Leaf databases of preprocessed reads from snapshot buffer b, on the
-// handle's stream once the reads still using the old leaves are done.
-static int build_prep(pir_db *db, int b)
+// handle's stream once the reads still using the old leaves are done: only
+// the leaf rows the epoch's dirty buckets feed when those are few (dirty =
+// their uploaded indices), else every row.
+static int build_prep(pir_db *db, int b, const uint64_t *dirty)
 {
     PIR_TRY(wait_readers(db, 2, db->stream));
+    if (dirty) {
+        HIP_TRY(launch_prep_rows(db->prep_t, db->buf[b], db->stride, db->n, db->prep_Nq, db->prep_Cq, dirty,
+                                 db->dirty.size(), db->prep, db->prep_leaf_bytes, db->stream));
+        return PIR_OK;
+    }
     HIP_TRY(launch_prep_d(db->prep_t, db->buf[b], db->stride, db->n, db->prep_Nq, db->prep_Cq, db->prep,
                           db->prep_leaf_bytes, db->stream));
     return PIR_OK;
@@ -568,9 +597,15 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
         return PIR_OK;
     }
     // publish: swap the copies (the leaf databases of preprocessed reads
-    // are rebuilt from the new snapshot first)
+    // are brought up to the new snapshot first: the leaf rows that this
+    // epoch's buckets feed while those buckets number at most a quarter of
+    // the leaf rows, else all of them)
+    const bool few = !db->all_dirty && !db->dirty.empty() && db->dirty.size() * 2 <= db->n;
+    const uint64_t *dirty_dev = nullptr;
+    if (few)
+        PIR_TRY(upload_dirty(db, &dirty_dev));
     if (db->prep)
-        PIR_TRY(build_prep(db, back));
+        PIR_TRY(build_prep(db, back, few && db->dirty.size() * 4 <= db->prep_Nq ? dirty_dev : nullptr));
     HIP_TRY(hipEventRecord(db->published, db->stream));
     const int old_front = db->front;
     db->front = back;
@@ -580,24 +615,12 @@ int pir_epoch_commit(pir_db *db, uint64_t *epoch_out)
     if (db->all_dirty || db->dirty.size() * 2 > db->n) {
         HIP_TRY(hipMemcpyAsync(db->buf[old_front], db->buf[db->front], db->n * db->stride, hipMemcpyDeviceToDevice,
                                db->stream));
-    } else if (!db->dirty.empty()) {
-        const uint64_t cnt = db->dirty.size();
-        PIR_TRY(wait_upload(db, UP_MIRROR));
-        if (cnt > db->mirror_idx_cap) {
-            if (db->mirror_idx_host)
-                hipHostFree(db->mirror_idx_host);
-            db->mirror_idx_host = nullptr;
-            db->mirror_idx_cap = 0;
-            void *p = nullptr;
-            PIR_TRY(host_mapped(cnt * sizeof(uint64_t), &p, &db->mirror_map));
-            db->mirror_idx_host = static_cast<uint64_t *>(p);
-            db->mirror_idx_cap = cnt;
-        }
-        memcpy(db->mirror_idx_host, db->dirty.data(), cnt * sizeof(uint64_t));
-        HIP_TRY(launch_copy_rows(db->buf[old_front], db->buf[db->front],
-                                 static_cast<const uint64_t *>(db->mirror_map), cnt, db->stride, db->stream));
-        PIR_TRY(note_upload(db, UP_MIRROR));
+    } else if (few) {
+        HIP_TRY(launch_copy_rows(db->buf[old_front], db->buf[db->front], dirty_dev, db->dirty.size(), db->stride,
+                                 db->stream));
     }
+    if (few)
+        PIR_TRY(note_upload(db, UP_MIRROR));
     // no host wait: the rest of the commit runs stream-ordered on the device
     for (uint64_t b : db->dirty)
         db->dirty_mark[b] = 0;
@@ -666,7 +689,7 @@ int pir_preprocess(pir_db *db, uint32_t levels, uint32_t min_batch)
     db->prep_Cq = Cq;
     // rows past Nq of every leaf stay zero (the kernels may read them)
     HIP_TRY(launch_fill_zero(db->prep, leaf_bytes * t.leaves, db->stream));
-    PIR_TRY(build_prep(db, db->front));
+    PIR_TRY(build_prep(db, db->front, nullptr));
     HIP_TRY(hipEventRecord(db->published, db->stream));
     return PIR_OK;
 }

@@ -119,6 +119,46 @@ __global__ __launch_bounds__(WG) void prep_d_kernel(const PrepTables t, const ui
     }
 }
 
+// The same leaf rows, for the rows that buckets idx[0 .. count) feed: bucket
+// b = i * Nq + x of the snapshot enters row x of a leaf through the leaf's
+// blocks of row-block i only, so after a commit that changed those buckets
+// the leaf rows x = b mod Nq are recomputed in full from the new snapshot
+// (two changed buckets with the same x recompute the same row to the same
+// bytes). Grid: x = leaf, y over the listed buckets; RB rows per workgroup as
+// in prep_d_kernel.
+__global__ __launch_bounds__(WG) void prep_rows_kernel(const PrepTables t, const uint4 *__restrict__ D,
+                                                       uint64_t stride16, uint64_t n, uint64_t Nq, uint32_t Cq16,
+                                                       const uint64_t *__restrict__ idx, uint64_t count,
+                                                       uint4 *__restrict__ out, uint64_t leaf_u4)
+{
+    const uint32_t leaf = blockIdx.x;
+    uint4 *o = out + leaf * leaf_u4;
+    const int cnt = t.d_cnt[leaf];
+    const uint32_t rb = Cq16 >= WG ? 1u : WG / Cq16;
+    const uint32_t rr = Cq16 >= WG ? 0u : threadIdx.x / Cq16;
+    const uint32_t c0 = Cq16 >= WG ? threadIdx.x : threadIdx.x % Cq16;
+    if (rr >= rb)
+        return;
+    for (uint64_t k = (uint64_t)blockIdx.y * rb + rr; k < count; k += (uint64_t)gridDim.y * rb) {
+        const uint64_t row = idx[k] % Nq;
+        for (uint32_t c16 = c0; c16 < Cq16; c16 += WG) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            for (int e = 0; e < cnt; ++e) {
+                const uint32_t blk = t.d[leaf][e];
+                const uint64_t src = (blk >> 4) * Nq + row;
+                if (src < n) {
+                    const uint4 x = D[src * stride16 + (blk & 15u) * Cq16 + c16];
+                    v.x ^= x.x;
+                    v.y ^= x.y;
+                    v.z ^= x.z;
+                    v.w ^= x.w;
+                }
+            }
+            o[row * Cq16 + c16] = v;
+        }
+    }
+}
+
 // Request-side leaf: out[row][w] = XOR over the leaf's blocks (i, j) of
 // word j * Wq + w of request row i * Bq + row; rows >= B and bits >= n read
 // as zero (no word wholly past bit n is read). Grid: x over the words of a
@@ -244,6 +284,20 @@ hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, ui
     hipLaunchKernelGGL(prep_d_kernel, dim3(t.leaves, chunks), dim3(WG), 0, stream, t,
                        static_cast<const uint4 *>(D), stride / 16, n, Nq, Cq16, static_cast<uint4 *>(out),
                        leaf_bytes / 16);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_rows(const PrepTables &t, const void *D, uint64_t stride, uint64_t n, uint64_t Nq, uint32_t Cq,
+                            const uint64_t *idx, uint64_t count, void *out, uint64_t leaf_bytes, hipStream_t stream)
+{
+    if (count == 0)
+        return hipSuccess;
+    const uint32_t Cq16 = Cq / 16;
+    const uint32_t rb = Cq16 >= WG ? 1u : WG / Cq16;
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + rb - 1) / rb, 65535));
+    hipLaunchKernelGGL(prep_rows_kernel, dim3(t.leaves, chunks), dim3(WG), 0, stream, t,
+                       static_cast<const uint4 *>(D), stride / 16, n, Nq, Cq16, idx, count,
+                       static_cast<uint4 *>(out), leaf_bytes / 16);
     return hipGetLastError();
 }
 

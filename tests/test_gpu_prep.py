@@ -138,3 +138,27 @@ def test_leaf_database_shapes(levels, n, d, z):
         for B in (2, 33):
             req = synth.bernoulli_requests(950 + B + z, B, n)
             assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"L={levels} n={n} bucket={d * z} B={B}")
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_commits_update_only_the_leaf_rows_they_feed(levels):
+    """A commit of a few buckets recomputes only the leaf rows those buckets
+    feed (buckets in different row blocks of one leaf row among them); a
+    commit of many rebuilds every leaf; every read after every commit equals
+    the oracle on the published snapshot."""
+    n, d, z, B = 1000, 2, 64, 40
+    nq = (-(-n // (1 << levels)) + 31) // 32 * 32   # bucket rows per block (the library pads to 32)
+    rng = np.random.default_rng(70 + levels)
+    D = synth.uniform_db(71, n, d * z)
+    req = synth.bernoulli_requests(72, B, n)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=1)
+        plans = [[5, 5 + nq], [0, n - 1, nq - 1], list(rng.choice(n, size=3, replace=False)),
+                 list(rng.choice(n, size=nq // 2, replace=False)), [7]]
+        for e, rows in enumerate(plans):
+            for b in rows:
+                D[b] = rng.integers(0, 256, d * z, dtype=np.uint8)
+                db.write_bucket(int(b), D[b])
+            db.commit()
+            assert_rows_equal(db.read(req), oracle.pir_read(D, req), f"L={levels} commit {e} ({len(rows)} buckets)")
