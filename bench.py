@@ -1,7 +1,9 @@
 """Benchmark of the XOR-PIR server path on one MI355X.
 
 Default workload: n = 2^22 buckets of 4 x 1 KiB (a 16 GiB database of uniform
-bytes), answering batches of B = 2048 Bernoulli(1/2) request vectors; then, as
+bytes), answering batches of B = 2048 Bernoulli(1/2) request vectors through two
+levels of Strassen leaves (formed once, then kept up to date by every commit for
+the rows its buckets feed); then, as
 a second case in the same line ("extra"), n = 65,536 buckets filled by
 blocked-cuckoo insertion of 200,000 synthetic messages (256 MiB), B = 256.
 
@@ -80,6 +82,12 @@ def kernel_source_digest(kind: int) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def summary_key(workload: str, levels: int) -> str:
+    """File-name key of a counter summary: the workload, and the Strassen levels
+    when the read goes through preprocessed leaves (counters per leaf launch)."""
+    return workload + (f"-strassen{levels}" if levels else "")
+
+
 def measured_valu(workload: str, plan) -> float | None:
     """VALU instructions per launch of the main read kernel (SQ_INSTS_VALU) from the
     committed counter summary, or None when it does not match this plan and source."""
@@ -146,7 +154,8 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str, calib_mib: 
     line = json.loads([x for x in open(bench_json) if x.startswith("{")][-1])
     plan = line["config"]["plan"]
     name = kernel_name(plan)
-    out = {"workload": line["config"]["workload"], "plan": plan,
+    levels = line["config"].get("strassen_levels", 0)
+    out = {"workload": summary_key(line["config"]["workload"], levels), "plan": plan,
            "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name,
            "calibration_copy_kib": calib_mib * 1024, "command": command}
     total = 0.0
@@ -175,7 +184,8 @@ def valu_summary(pmc_dir: str, bench_json: str, command: str):
     line = json.loads([x for x in open(bench_json) if x.startswith("{")][-1])
     plan = line["config"]["plan"]
     name = kernel_name(plan)
-    out = {"workload": line["config"]["workload"], "plan": plan,
+    levels = line["config"].get("strassen_levels", 0)
+    out = {"workload": summary_key(line["config"]["workload"], levels), "plan": plan,
            "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name, "command": command}
     for counter, key in (("SQ_INSTS_VALU", "valu_insts_per_launch"), ("SQ_INSTS_SALU", "salu_insts_per_launch"),
                          ("SQ_INSTS_LDS", "lds_insts_per_launch"), ("GRBM_GUI_ACTIVE", "gui_active_per_launch")):
@@ -455,8 +465,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="c4a: skip the 256 MiB second case")
     ap.add_argument("--read-streams", type=int, default=1,
                     help="read streams that consecutive batches take in turn (1 = every batch on one stream)")
-    ap.add_argument("--prep", type=int, default=0, choices=[0, 1, 2],
-                    help="answer through L levels of Strassen leaves formed at commit (large batches)")
+    ap.add_argument("--prep", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="answer through L levels of Strassen leaves formed at commit and kept up to date row by "
+                         "row (default: 2 for the 16 GiB workload, else 0)")
     ap.add_argument("--time-every", type=int, default=5,
                     help="time the main kernel of every k-th timed read with HIP events (1 = all)")
     ap.add_argument("--masked", action="store_true",
@@ -490,14 +501,21 @@ def main():
     key = args.workload
     w = WORKLOADS[key]
     B = args.B or w.B or 1024
+    if args.prep < 0:
+        # Strassen leaves (maintained row by row at every commit) for the
+        # 2048-request batches of the 16 GiB database, the plain read elsewhere
+        args.prep = 2 if key == "c4a" and not (args.kind or args.masked or args.B) else 0
     big = w.db_bytes > (1 << 30)
     cpu_rows = args.cpu_rows or (16 if big else B)
     cpu_single = args.cpu_rows_single if args.cpu_rows_single >= 0 else (2 if big else 16)
     line = fixed_bench(args, pir, torch, w, B, args.steps, args.warmup, cpu_rows, cpu_single,
                        latency=args.latency_reads)
-    if key == "c4a" and not args.no_extra and not (args.kind or args.prep or args.masked or args.B):
-        # the paper-scale 256 MiB database as a second, cache-sized case
+    if key == "c4a" and not args.no_extra and not (args.kind or args.masked or args.B):
+        # the paper-scale 256 MiB database as a second, cache-sized case (plain
+        # read: its 256-request batches are below the leaves' threshold)
+        levels, args.prep = args.prep, 0
         sub = fixed_bench(args, pir, torch, configs.C2, configs.C2.B, 50, 5, 16, 0, latency=50)
+        args.prep = levels
         line["extra"] = {"c2": {k: sub[k] for k in ("value", "ms_per_step", "config", "roofline", "cpu_baseline",
                                                    "parity_sampled", "read_latency_ms")}}
     print(json.dumps(line), flush=True)
@@ -726,8 +744,25 @@ def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "achieved_is": "algorithmic bytes (database once, requests, answers) per second of the main "
                                "read kernel"}
-    roof["traffic"] = measured_traffic(w.name, plan)
-    lds = None if args.prep else lds_floor(plan, w.n, B, w.bucket_bytes)
+    # With Strassen leaves the main kernel runs once per leaf (7^L launches of
+    # n/2^L buckets x d*z/2^L bytes x B/2^L requests); its figures are summed
+    # over the read's leaves and kern_ms spans the first leaf's start to the
+    # last one's end.
+    leaves = 7 ** args.prep if args.prep else 1
+    key = summary_key(w.name, args.prep)
+    traffic = measured_traffic(key, plan)
+    roof["traffic"] = None if traffic is None else traffic * leaves
+    if args.prep:
+        unit = 32 << args.prep
+        nq, bq, cq = -(-w.n // unit) * unit >> args.prep, -(-B // (1 << args.prep)), w.bucket_bytes >> args.prep
+        # the leaves take the automatic plan of their shape: the same family as
+        # this batch's while both are above 128 requests
+        one = lds_floor(plan, nq, bq, cq) if bq > 128 and B > 128 else None
+        lds = None if one is None else {"read_bytes": one["read_bytes"] * leaves,
+                                        "write_bytes": one["write_bytes"] * leaves,
+                                        "floor_ms": round(one["floor_ms"] * leaves, 4), "leaves": leaves}
+    else:
+        lds = lds_floor(plan, w.n, B, w.bucket_bytes)
     if lds:
         lds["frac"] = round(lds["floor_ms"] / kern_ms, 4)   # of the LDS-bound floor
         roof["lds"] = lds
@@ -735,10 +770,10 @@ def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_
     roof.update(kernel_ms=round(kern_ms, 4), hbm_gbs_alg=round(hbm_achieved, 1),
                 hbm_frac=round(hbm_achieved / HBM_PEAK_GBS, 4), plain_xor_tops=round(alu_achieved, 3),
                 valu_frac=round(alu_achieved / VALU_PEAK_TOPS, 4), alg_bytes=alg_bytes, plain_xor_ops=xor_ops)
-    inst = measured_valu(w.name, plan)
+    inst = measured_valu(key, plan)
     if inst is not None:
         # VALU instructions the kernel really executes (counter summary), as lane-operations per second
-        roof["valu_executed_frac"] = round(inst * 64 / t_kernel / (VALU_PEAK_TOPS * 1e12), 4)
+        roof["valu_executed_frac"] = round(inst * leaves * 64 / t_kernel / (VALU_PEAK_TOPS * 1e12), 4)
 
     cpu = None
     parity = None
