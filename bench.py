@@ -205,7 +205,7 @@ def popcount_rows(req: np.ndarray, n: int) -> np.ndarray:
     return bits.sum(axis=1, dtype=np.int64)
 
 
-def serve_bench(args, pir):
+def serve_bench(args, pir, rates=None, duration=None, warmup_s=None, probes=None, baseline=True, emit=True):
     """Serving workload: open-loop Poisson reads with 10% writes published every
     epoch, each read returning its answer and the global interest vector.
 
@@ -220,7 +220,9 @@ def serve_bench(args, pir):
     w = configs.C5
     x = w.extra
     iv_bits = args.iv_bits or x["interest_bits"]
-    dur, warm = args.duration, args.warmup_s
+    dur = args.duration if duration is None else duration
+    warm = args.warmup_s if warmup_s is None else warmup_s
+    n_probes = args.probes if probes is None else probes
     t = time.perf_counter()
     db = pir.PirDB(w.n, w.d, w.z)
     db.interest_config(iv_bits, x["window"])
@@ -251,7 +253,7 @@ def serve_bench(args, pir):
             deltas.setdefault(int(e), []).append(ipos[wep == e].reshape(-1))
         return wep
 
-    for rate in [r for r in x["rates"] if not args.rates or r in args.rates]:
+    for rate in rates or [r for r in x["rates"] if not args.rates or r in args.rates]:
         span = warm + dur
         read_t = synth.poisson_arrivals(x["arrival_seed"] + rate, rate, span)
         rows = synth.uniform_indices(x["arrival_seed"] + rate + 1, read_t.size, 1024).astype(np.uint32)
@@ -261,7 +263,7 @@ def serve_bench(args, pir):
         ipos = synth.interest_positions(x["arrival_seed"] + rate + 4, write_t.size, x["interest_k"], iv_bits)
         row = {"rate": rate, "reads": int(read_t.size), "writes": int(write_t.size)}
         for mode, mb, lanes in (("batched", args.max_batch, args.lanes), ("one_per_read", 1, 4)):
-            if mode == "one_per_read" and args.no_baseline:
+            if mode == "one_per_read" and (args.no_baseline or not baseline):
                 continue
             # the one-launch-per-read baseline is given a shorter slice of the same trace
             n_r = read_t.size if mode == "batched" else int(np.searchsorted(read_t, min(span, args.baseline_s)))
@@ -269,7 +271,7 @@ def serve_bench(args, pir):
             post = np.nonzero(read_t[:n_r] >= (warm if mode == "batched" else 0.0))[0]
             probe = None
             if mode == "batched" and ref is not None and post.size:
-                probe = post[np.unique(np.linspace(0, post.size - 1, args.probes).round().astype(np.int64))]
+                probe = post[np.unique(np.linspace(0, post.size - 1, n_probes).round().astype(np.int64))]
             log(f"[serve] rate {rate}/s {mode}: {n_r} reads, {n_w} writes")
             wsl = tuple(a[:n_w] for a in writes)
             out = pir.serve(db, ck, read_t=read_t[:n_r], read_row=rows[:n_r], req_pool=pool,
@@ -340,7 +342,9 @@ def serve_bench(args, pir):
         "parity_reads_checked": checked,
         "serving": results,
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def stream_bench(args, pir, torch):
@@ -514,10 +518,24 @@ def main():
         # the paper-scale 256 MiB database as a second, cache-sized case (plain
         # read: its 256-request batches are below the leaves' threshold)
         levels, args.prep = args.prep, 0
+        keep = ("value", "ms_per_step", "config", "roofline", "cpu_baseline", "parity_sampled", "read_latency_ms")
         sub = fixed_bench(args, pir, torch, configs.C2, configs.C2.B, 50, 5, 16, 0, latency=50)
+        line["extra"] = {"c2": {k: sub[k] for k in keep}}
+        # a small batch over a database larger than the caches (4 GiB, B = 64):
+        # the HBM-bound regime
+        sub = fixed_bench(args, pir, torch, configs.C3B64, configs.C3B64.B, 20, 3, 4, 0, latency=20)
+        line["extra"]["b64_4GiB"] = {k: sub[k] for k in keep}
         args.prep = levels
-        line["extra"] = {"c2": {k: sub[k] for k in ("value", "ms_per_step", "config", "roofline", "cpu_baseline",
-                                                   "parity_sampled", "read_latency_ms")}}
+        # serving: 20k Poisson reads/s over 4 GiB for 5 s after 1 s, each with the
+        # 128 KiB interest vector, 16 probed reads against the oracle's replay
+        srv = serve_bench(args, pir, rates=[20_000], duration=5.0, warmup_s=1.0, probes=16, baseline=False,
+                          emit=False)
+        b = srv["serving"][0]["batched"]
+        line["extra"]["serving"] = {"workload": srv["config"]["workload"], "offered_reads_per_s": 20_000,
+                                    "served_reads_per_s": b["reads_per_s"], "p50_ms": b["p50_ms"],
+                                    "p99_ms": b["p99_ms"], "max_ms": b["max_ms"], "duration_s": 5.0,
+                                    "interest_bits": srv["config"]["interest_bits"], "parity": srv["parity"],
+                                    "parity_reads_checked": srv["parity_reads_checked"]}
     print(json.dumps(line), flush=True)
 
 

@@ -157,9 +157,10 @@ int pir_read_batch_noalloc_async(pir_db *db, const void *d_req, uint64_t req_pit
  * of d_req and writes response rows resp_first[k] .. of d_resp (row indices,
  * host arrays; a NULL array means the batches' rows are concatenated in
  * order). Every batch is answered exactly as pir_read_batch_async would
- * answer it. Consecutive batches are fused into launch groups of at least
- * 256 requests (an answer depends only on its own request row and the
- * snapshot), each answered by one read launch with that group's schedule;
+ * answer it. The stream's rows, in order, are cut into launch groups of 1024
+ * requests (a batch may straddle two groups; the last group takes the rest:
+ * an answer depends only on its own request row and the snapshot), each
+ * answered by one read launch with that group's schedule;
  * rows that are not contiguous are gathered into / scattered from library
  * scratch on the stream. The launch sequence is captured in a HIP graph and
  * replayed when the same stream shape, buffers, schedules and snapshot

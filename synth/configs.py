@@ -43,6 +43,7 @@ C2 = Workload("xorpir-n65536-d4-z1k-B256-cuckoo200k", n=65536, d=4, z=1 * KiB, B
               fill="cuckoo", cuckoo_items=200_000, cuckoo_seed=3002)
 C3 = Workload("xorpir-n1M-d4-z1k-uneven500", n=1 << 20, d=4, z=1 * KiB, db_seed=1003, req_seed=2003,
               batches=500, batch_seed=5003)
+C3B64 = Workload("xorpir-n1M-d4-z1k-B64", n=1 << 20, d=4, z=1 * KiB, B=64, db_seed=1003, req_seed=2003)
 C4A = Workload("xorpir-n4M-d4-z1k-B2048", n=1 << 22, d=4, z=1 * KiB, B=2048, db_seed=1004, req_seed=2004)
 C4B = Workload("xorpir-n1M-d2-z4k-B2048", n=1 << 20, d=2, z=4 * KiB, B=2048, db_seed=1014, req_seed=2014)
 C5 = Workload("serve-n1M-d4-z1k", n=1 << 20, d=4, z=1 * KiB, fill="cuckoo", cuckoo_items=3_145_728,
@@ -50,7 +51,7 @@ C5 = Workload("serve-n1M-d4-z1k", n=1 << 20, d=4, z=1 * KiB, fill="cuckoo", cuck
               extra={"arrival_seed": 4005, "rates": (5_000, 20_000, 50_000), "write_frac": 0.1,
                      "interest_bits": 1 << 20, "interest_k": 6, "window": 100, "epoch_s": 1.0})
 
-ALL = {w.name: w for w in (C1, C2, C3, C4A, C4B, C5)}
+ALL = {w.name: w for w in (C1, C2, C3, C3B64, C4A, C4B, C5)}
 BY_KEY = {"c1": C1, "c2": C2, "c3": C3, "c4a": C4A, "c4b": C4B, "c5": C5}
 
 # Blocked cuckoo parameters shared by every cuckoo-filled workload.
