@@ -151,7 +151,6 @@ int encode_interest(pir_db *db, const uint32_t *words, uint64_t m, uint8_t *out,
 // Record that stream s reads buffer b (commits wait for it before reusing b).
 int note_reader(pir_db *db, int b, hipStream_t s);
 int reader_event(pir_db *db, int b, hipStream_t s, hipEvent_t *ev);
-int wait_published(pir_db *db, hipStream_t s);
 // Tuning table lookup: true and *p if an entry exists for (n, B class, stride).
 bool tune_lookup(uint64_t n, uint32_t B, uint64_t stride, Plan *p);
 }  // namespace talek

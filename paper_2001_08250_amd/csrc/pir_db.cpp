@@ -716,25 +716,53 @@ static int profile_slot(pir_db *db, hipEvent_t *eb, hipEvent_t *ee)
     return PIR_OK;
 }
 
-// Preprocessed read of B request rows q (device, pitch qp, 4-byte aligned
-// words) into out (pitch op): the request blocks of every leaf, the 7^L leaf
-// products with the Four-Russians kernels, then the answers from the
-// products (masked in place when keys are given). `done` is recorded by the
-// last kernel; eb / ee take the start of the first leaf's main kernel and
-// the end of the last one's.
-static int prep_read(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, void *out, uint64_t op,
-                     const uint32_t *keys, hipStream_t s, hipEvent_t eb, hipEvent_t ee, hipEvent_t done)
+// Sizes of a preprocessed read of B rows: Bq request blocks of Nq bits
+// (Wq words, pitch qpl) per leaf, Cq-byte leaf answers, and the per-leaf
+// spans of the request and answer scratch.
+struct LeafShape {
+    uint32_t Bq;
+    uint64_t Nq, Wq, qpl, q_leaf, o_leaf;
+    uint32_t Cq;
+};
+
+static LeafShape leaf_shape(const pir_db *db, uint32_t B)
+{
+    LeafShape l{};
+    l.Bq = (B + db->prep_t.grid - 1) / db->prep_t.grid;
+    l.Nq = db->prep_Nq;
+    l.Wq = l.Nq / 32;
+    l.Cq = db->prep_Cq;
+    l.qpl = (l.Wq * 4 + 15) & ~15ull;                   // leaf request pitch
+    l.q_leaf = ((uint64_t)l.Bq * l.qpl + 255) & ~255ull;
+    l.o_leaf = ((uint64_t)l.Bq * l.Cq + 255) & ~255ull;
+    return l;
+}
+
+// The request blocks of every leaf (they depend on the requests only, not on
+// the snapshot, so a read enqueues them before it waits for the latest
+// publication and, on its own stream, they can run beside another read).
+static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, hipStream_t s)
 {
     const PrepTables &t = db->prep_t;
-    const uint32_t Bq = (B + t.grid - 1) / t.grid;
-    const uint64_t Nq = db->prep_Nq, Wq = Nq / 32;
-    const uint32_t Cq = db->prep_Cq;
-    const uint64_t qpl = (Wq * 4 + 15) & ~15ull;        // leaf request pitch
-    const uint64_t q_leaf = ((uint64_t)Bq * qpl + 255) & ~255ull;
-    const uint64_t o_leaf = ((uint64_t)Bq * Cq + 255) & ~255ull;
-    PIR_TRY(ensure_device(&sc.leaf_q, &sc.leaf_q_cap, q_leaf * t.leaves));
-    PIR_TRY(ensure_device(&sc.leaf_out, &sc.leaf_out_cap, o_leaf * t.leaves));
-    HIP_TRY(launch_prep_q(t, q, qp, B, db->n, Bq, Wq, sc.leaf_q, qpl, q_leaf, s));
+    const LeafShape l = leaf_shape(db, B);
+    PIR_TRY(ensure_device(&sc.leaf_q, &sc.leaf_q_cap, l.q_leaf * t.leaves));
+    PIR_TRY(ensure_device(&sc.leaf_out, &sc.leaf_out_cap, l.o_leaf * t.leaves));
+    HIP_TRY(launch_prep_q(t, q, qp, B, db->n, l.Bq, l.Wq, sc.leaf_q, l.qpl, l.q_leaf, s));
+    return PIR_OK;
+}
+
+// Preprocessed read of B rows, whose request blocks prep_requests formed on
+// stream s, into out (pitch op): the 7^L leaf products with the
+// Four-Russians kernels, then the answers from the products (masked in place
+// when keys are given). `done` is recorded by the last kernel; eb / ee take
+// the start of the first leaf's main kernel and the end of the last one's.
+static int prep_read(pir_db *db, Scratch &sc, uint32_t B, void *out, uint64_t op, const uint32_t *keys,
+                     hipStream_t s, hipEvent_t eb, hipEvent_t ee, hipEvent_t done)
+{
+    const PrepTables &t = db->prep_t;
+    const LeafShape l = leaf_shape(db, B);
+    const uint32_t Bq = l.Bq, Cq = l.Cq;
+    const uint64_t Nq = l.Nq, qpl = l.qpl, q_leaf = l.q_leaf, o_leaf = l.o_leaf;
     ReadGeom g{};
     g.n = Nq;
     g.stride = Cq;
@@ -796,7 +824,8 @@ static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint
     hipEvent_t eb, ee;
     PIR_TRY(profile_slot(db, &eb, &ee));
     if (use_prep(db, B)) {
-        PIR_TRY(prep_read(db, sc, sc.req, qp, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
+        PIR_TRY(prep_requests(db, sc, sc.req, qp, B, db->stream));
+        PIR_TRY(prep_read(db, sc, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
     } else {
         Plan p = choose_plan(db, B);
         PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
@@ -821,7 +850,6 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     std::lock_guard<std::recursive_mutex> lk(db->mu);
     HIP_TRY(hipSetDevice(db->device));
-    PIR_TRY(wait_published(db, s));
     Scratch &sc = scratch_for(db, s);
     const void *q = d_req;
     uint64_t qp = req_pitch;
@@ -833,6 +861,12 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
         q = sc.req;
         qp = db->qpitch;
     }
+    // work that needs only the requests goes out before the wait for the
+    // latest publication
+    const bool prep = use_prep(db, B);
+    if (prep)
+        PIR_TRY(prep_requests(db, sc, q, qp, B, s));
+    PIR_TRY(wait_published(db, s));
     const bool direct = !(reinterpret_cast<uintptr_t>(d_resp) & 15) && !(resp_pitch & 15) &&
                         db->stride == db->bucket_bytes;
     void *out = d_resp;
@@ -846,10 +880,9 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     g.keys = static_cast<const uint32_t *>(d_keys);
     hipEvent_t eb, ee, done;
     PIR_TRY(profile_slot(db, &eb, &ee));
-    const bool prep = use_prep(db, B);
     PIR_TRY(reader_event(db, prep ? 2 : db->front, s, &done));
     if (prep) {
-        PIR_TRY(prep_read(db, sc, q, qp, B, out, op, g.keys, s, eb, ee, direct ? done : nullptr));
+        PIR_TRY(prep_read(db, sc, B, out, op, g.keys, s, eb, ee, direct ? done : nullptr));
     } else {
         Plan p = choose_plan(db, B);
         PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
