@@ -84,34 +84,35 @@ def kernel_source_digest(kind: int) -> str:
 
 def summary_key(workload: str, levels: int) -> str:
     """File-name key of a counter summary: the workload, and the Strassen levels
-    when the read goes through preprocessed leaves (counters per leaf launch)."""
+    when the read goes through preprocessed leaves."""
     return workload + (f"-strassen{levels}" if levels else "")
 
 
-def measured_valu(workload: str, plan) -> float | None:
-    """VALU instructions per launch of the main read kernel (SQ_INSTS_VALU) from the
-    committed counter summary, or None when it does not match this plan and source."""
-    path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
+def _summary(kind: str, workload: str, plan):
+    """The committed counter summary profiles/<kind>_<workload>.json, or None when
+    none matches this workload and plan or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}.json")
     if not os.path.isfile(path):
         return None
     t = json.load(open(path))
     want = {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll, "flags": plan.flags}
     if t.get("plan") != want or t.get("kernel_source_sha256_16") != kernel_source_digest(plan.kind):
         return None
-    return float(t["valu_insts_per_launch"])
+    return t
+
+
+def measured_valu(workload: str, plan) -> float | None:
+    """VALU instructions (SQ_INSTS_VALU) of the main read kernel per read, from the
+    committed counter summary (per launch times its launches per read)."""
+    t = _summary("valu", workload, plan)
+    return None if t is None else float(t["valu_insts_per_launch"]) * float(t.get("launches_per_read", 1))
 
 
 def measured_traffic(workload: str, plan) -> float | None:
-    """HBM bytes per read launch from the committed counter summary, or None when
-    no summary matches this workload and plan or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    if not os.path.isfile(path):
-        return None
-    t = json.load(open(path))
-    want = {"kind": plan.kind, "tile": plan.tile, "splits": plan.splits, "unroll": plan.unroll, "flags": plan.flags}
-    if t.get("plan") != want or t.get("kernel_source_sha256_16") != kernel_source_digest(plan.kind):
-        return None
-    return float(t["hbm_bytes_per_launch"])
+    """HBM bytes of the main read kernel per read, from the committed counter
+    summary (per launch times its launches per read)."""
+    t = _summary("traffic", workload, plan)
+    return None if t is None else float(t["hbm_bytes_per_launch"]) * float(t.get("launches_per_read", 1))
 
 
 KERNEL_NAMES = {1: "xorpir_tile_kernel", 2: "xorpir_tile_kernel", 3: "xorpir_m4r_kernel",
@@ -137,6 +138,18 @@ def _counter_rows(d: str, counter: str):
     if not rows:
         raise SystemExit(f"no {counter} rows under {d}")
     return rows
+
+
+def _launches_per_read(rows, name: str, levels: int) -> float:
+    """Main-kernel launches per read in a profiled run: 1 for a plain read; for
+    a preprocessed one, its launches over the reads' final combining kernels."""
+    if not levels:
+        return 1.0
+    main = {r["Dispatch_Id"] for r in rows if name in r["Kernel_Name"]}
+    reads = {r["Dispatch_Id"] for r in rows if "prep_out_kernel" in r["Kernel_Name"]}
+    if not reads:
+        raise SystemExit("no prep_out_kernel dispatches in a preprocessed run")
+    return len(main) / len(reads)
 
 
 def _calibration_dispatch(rows):
@@ -170,6 +183,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str, calib_mib: 
         out[counter.lower()] = {"copy_kib": copy_kib, "factor": round(factor, 4), "kernel_kib_mean": kib,
                                 "dispatches": len(vals), "bytes": kib * factor * 1024}
         total += kib * factor * 1024
+        out["launches_per_read"] = _launches_per_read(rows, name, levels)
     out["hbm_bytes_per_launch"] = round(total)
     path = os.path.join(ROOT, "profiles", f"traffic_{out['workload']}.json")
     with open(path, "w") as fh:
@@ -189,11 +203,13 @@ def valu_summary(pmc_dir: str, bench_json: str, command: str):
            "kernel_source_sha256_16": kernel_source_digest(plan["kind"]), "kernel": name, "command": command}
     for counter, key in (("SQ_INSTS_VALU", "valu_insts_per_launch"), ("SQ_INSTS_SALU", "salu_insts_per_launch"),
                          ("SQ_INSTS_LDS", "lds_insts_per_launch"), ("GRBM_GUI_ACTIVE", "gui_active_per_launch")):
-        vals = [float(r["Counter_Value"]) for r in _counter_rows(pmc_dir, counter) if name in r["Kernel_Name"]]
+        rows = _counter_rows(pmc_dir, counter)
+        vals = [float(r["Counter_Value"]) for r in rows if name in r["Kernel_Name"]]
         if not vals:
             raise SystemExit(f"no {name} dispatches with {counter} in {pmc_dir}")
         out[key] = float(np.mean(vals))
         out["dispatches"] = len(vals)
+        out["launches_per_read"] = _launches_per_read(rows, name, levels)
     path = os.path.join(ROOT, "profiles", f"valu_{out['workload']}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -462,9 +478,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--cpu-rows", type=int, default=0,
-                    help="oracle rows on all host cores (default: every row up to 1 GiB databases, else 16)")
+                    help="oracle rows on all host cores (default: every row up to 1 GiB databases, else 48)")
     ap.add_argument("--cpu-rows-single", type=int, default=-1,
-                    help="oracle rows on one core (default: 2 over databases above 1 GiB, else 16)")
+                    help="oracle rows on one core (default: 4 over databases above 1 GiB, else 16)")
     ap.add_argument("--latency-reads", type=int, default=20, help="batches issued alone for the latency figures")
     ap.add_argument("--no-extra", action="store_true", help="c4a: skip the 256 MiB second case")
     ap.add_argument("--read-streams", type=int, default=1,
@@ -510,8 +526,10 @@ def main():
         # 2048-request batches of the 16 GiB database, the plain read elsewhere
         args.prep = 2 if key == "c4a" and not (args.kind or args.masked or args.B) else 0
     big = w.db_bytes > (1 << 30)
-    cpu_rows = args.cpu_rows or (16 if big else B)
-    cpu_single = args.cpu_rows_single if args.cpu_rows_single >= 0 else (2 if big else 16)
+    # oracle sample: about 10 s on all host cores and 8 s on one over the 16 GiB
+    # database (5 and 0.5 reads/s)
+    cpu_rows = args.cpu_rows or (48 if big else B)
+    cpu_single = args.cpu_rows_single if args.cpu_rows_single >= 0 else (4 if big else 16)
     line = fixed_bench(args, pir, torch, w, B, args.steps, args.warmup, cpu_rows, cpu_single,
                        latency=args.latency_reads)
     if key == "c4a" and not args.no_extra and not (args.kind or args.masked or args.B):
@@ -762,14 +780,15 @@ def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_
                 "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "achieved_is": "algorithmic bytes (database once, requests, answers) per second of the main "
                                "read kernel"}
-    # With Strassen leaves the main kernel runs once per leaf (7^L launches of
-    # n/2^L buckets x d*z/2^L bytes x B/2^L requests); its figures are summed
-    # over the read's leaves and kern_ms spans the first leaf's start to the
-    # last one's end.
+    # With Strassen leaves the main kernel answers 7^L leaves (products of
+    # n/2^L buckets x d*z/2^L bytes x B/2^L requests), in one launch when their
+    # offsets are staged together (else one launch per leaf); its figures are
+    # summed over the read's leaves and kern_ms spans the first leaf's start to
+    # the last one's end.
     leaves = 7 ** args.prep if args.prep else 1
     key = summary_key(w.name, args.prep)
     traffic = measured_traffic(key, plan)
-    roof["traffic"] = None if traffic is None else traffic * leaves
+    roof["traffic"] = traffic
     if args.prep:
         unit = 32 << args.prep
         nq, bq, cq = -(-w.n // unit) * unit >> args.prep, -(-B // (1 << args.prep)), w.bucket_bytes >> args.prep
@@ -791,7 +810,7 @@ def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_
     inst = measured_valu(key, plan)
     if inst is not None:
         # VALU instructions the kernel really executes (counter summary), as lane-operations per second
-        roof["valu_executed_frac"] = round(inst * leaves * 64 / t_kernel / (VALU_PEAK_TOPS * 1e12), 4)
+        roof["valu_executed_frac"] = round(inst * 64 / t_kernel / (VALU_PEAK_TOPS * 1e12), 4)
 
     cpu = None
     parity = None

@@ -468,13 +468,19 @@ int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
  * (1 or 2) of Strassen's block recursion, whose seven block products per
  * level need only XORs over GF(2): the database side of every one of the
  * 7^L leaf products (an XOR of up to 2^L blocks of the snapshot) is formed
- * once per epoch commit, and a read forms the request blocks, answers the
- * 7^L leaf products with the usual kernels and XORs them into the answers.
- * The answers are exactly those of the plain definition; a large read does
- * 7^L / 8^L of the plain product's work, at the price of 7^L / 4^L times the
- * snapshot in device memory (1.75 at L = 1, 3.06 at L = 2) and one pass over
- * it in every commit that changes the snapshot (the delay before writes
- * become readable grows by that pass).
+ * once and kept up to date by every epoch commit (a commit recomputes the
+ * leaf rows its changed buckets feed, or every leaf when they exceed a
+ * quarter of the rows), and a read forms the request side of every leaf
+ * (under the paired-table kernels: the table offsets of all leaves' request
+ * rows in one launch), answers the 7^L leaf products with the usual kernels
+ * (in one launch when the offsets were staged together) and XORs them into
+ * the answers. The answers are exactly those of the plain definition; a
+ * large read does 7^L / 8^L of the plain product's work, at the price of
+ * 7^L / 4^L times the snapshot in device memory (1.75 at L = 1, 3.06 at
+ * L = 2), the commits' leaf upkeep, and per-read scratch of about
+ * 7^L * (n / 2^L / 10 + 1) * ceil(B / 2^L) * 4 bytes of staged offsets plus
+ * the leaves' split partials (10.5 GB and 3.2 GB for 2048 requests over
+ * 2^22 buckets of 4 KiB at L = 2).
  *
  *   levels:    0 (off, frees the leaves), 1 or 2.
  *   min_batch: reads of B >= min_batch rows take the preprocessed path

@@ -37,6 +37,15 @@ struct ReadGeom {
     // Event that the read's last kernel records when it completes (through
     // the dispatch itself, so no separate marker sits in the stream), or none.
     hipEvent_t done = nullptr;
+    // Pair-table reads only: offsets already staged in the layout the read's
+    // own staging kernel writes (launch_stage_leaf_pairs), or none.
+    const uint32_t *staged = nullptr;
+    // Pair-table reads of staged offsets only: `leaves` products of this
+    // shape in one launch, leaf l's database at D + l * leaf_d_bytes and
+    // offsets at staged + l * leaf_stage_bytes, its answers rows l * B ..
+    // l * B + B - 1 of out (pitch out_pitch).
+    uint32_t leaves = 1;
+    uint64_t leaf_d_bytes = 0, leaf_stage_bytes = 0;
 };
 
 struct Plan {
@@ -162,6 +171,16 @@ struct PrepTables {
     uint8_t o_leaf[PREP_MAX_BLOCKS][16];
 };
 bool prep_tables(uint32_t levels, PrepTables *t);
+// Whether launch_stage_leaf_pairs serves leaf reads of geometry g (n, B, the
+// leaf's) under plan p, and the bytes it stages per leaf.
+bool leaf_staging_supported(const ReadGeom &g, const Plan &p, uint32_t leaves);
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p);
+// The pair-table offsets of every leaf's request rows (leaf i at
+// staged + i * leaf_bytes), staged from the B request rows Q (pitch qpitch
+// bytes, 4-byte aligned, n bits) of a read.
+hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n,
+                                   const ReadGeom &g, const Plan &p, void *staged, uint64_t leaf_bytes,
+                                   hipStream_t stream);
 // Leaf databases: leaf i (leaf_bytes apart, rows Cq bytes) = XOR of its D
 // blocks, rows Nq per block (rows >= n of D read as zero).
 hipError_t launch_prep_d(const PrepTables &t, const void *D, uint64_t stride, uint64_t n, uint64_t Nq, uint32_t Cq,

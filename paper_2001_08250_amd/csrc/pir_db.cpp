@@ -738,52 +738,101 @@ static LeafShape leaf_shape(const pir_db *db, uint32_t B)
     return l;
 }
 
-// The request blocks of every leaf (they depend on the requests only, not on
-// the snapshot, so a read enqueues them before it waits for the latest
-// publication and, on its own stream, they can run beside another read).
-static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, hipStream_t s)
-{
-    const PrepTables &t = db->prep_t;
-    const LeafShape l = leaf_shape(db, B);
-    PIR_TRY(ensure_device(&sc.leaf_q, &sc.leaf_q_cap, l.q_leaf * t.leaves));
-    PIR_TRY(ensure_device(&sc.leaf_out, &sc.leaf_out_cap, l.o_leaf * t.leaves));
-    HIP_TRY(launch_prep_q(t, q, qp, B, db->n, l.Bq, l.Wq, sc.leaf_q, l.qpl, l.q_leaf, s));
-    return PIR_OK;
-}
+// Staged offsets of all leaves of one read above this many bytes go back to
+// leaf request rows and a staging kernel per leaf; split partials of all
+// leaves above this many bytes, to a launch per leaf.
+constexpr uint64_t PREP_STAGE_MAX = 32ull << 30;
+constexpr uint64_t PREP_PARTIAL_MAX = 8ull << 30;
 
-// Preprocessed read of B rows, whose request blocks prep_requests formed on
-// stream s, into out (pitch op): the 7^L leaf products with the
-// Four-Russians kernels, then the answers from the products (masked in place
-// when keys are given). `done` is recorded by the last kernel; eb / ee take
-// the start of the first leaf's main kernel and the end of the last one's.
-static int prep_read(pir_db *db, Scratch &sc, uint32_t B, void *out, uint64_t op, const uint32_t *keys,
-                     hipStream_t s, hipEvent_t eb, hipEvent_t ee, hipEvent_t done)
+// A preprocessed read's leaf geometry (D, Q and out set per leaf), plan,
+// what sc.leaf_q holds per leaf (the pair-table offsets of its request rows
+// when staged, else the rows themselves), the bytes per leaf answer block in
+// sc.leaf_out, and whether one launch answers every leaf.
+struct LeafRead {
+    LeafShape l;
+    ReadGeom g;
+    Plan p;
+    bool staged, fused;
+    uint64_t q_leaf, o_leaf;
+};
+
+// The request side of every leaf: it depends on the requests only, not on
+// the snapshot, so a read enqueues it before it waits for the latest
+// publication. Under a pair-table plan one launch stages every leaf's
+// table offsets straight from the request rows; otherwise the leaves'
+// request rows are formed for their reads to stage.
+static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, hipStream_t s,
+                         LeafRead *lr)
 {
     const PrepTables &t = db->prep_t;
-    const LeafShape l = leaf_shape(db, B);
-    const uint32_t Bq = l.Bq, Cq = l.Cq;
-    const uint64_t Nq = l.Nq, qpl = l.qpl, q_leaf = l.q_leaf, o_leaf = l.o_leaf;
-    ReadGeom g{};
-    g.n = Nq;
-    g.stride = Cq;
-    g.qpitch = qpl;
-    g.B = Bq;
-    g.out_pitch = Cq;
+    lr->l = leaf_shape(db, B);
+    const LeafShape &l = lr->l;
+    ReadGeom &g = lr->g;
+    g = ReadGeom{};
+    g.n = l.Nq;
+    g.stride = l.Cq;
+    g.qpitch = l.qpl;
+    g.B = l.Bq;
+    g.out_pitch = l.Cq;
     Plan want = db->forced;
     if (want.kind == KIND_AUTO) {
         Plan tuned;
-        if (tune_lookup(Nq, Bq, Cq, &tuned))
+        if (tune_lookup(l.Nq, l.Bq, l.Cq, &tuned))
             want = tuned;
     }
-    const Plan p = resolve_plan(g, want, db->num_cus);
-    PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
-    for (uint32_t l = 0; l < t.leaves; ++l) {
-        g.D = db->prep + l * db->prep_leaf_bytes;
-        g.Q = static_cast<uint8_t *>(sc.leaf_q) + l * q_leaf;
-        g.out = static_cast<uint8_t *>(sc.leaf_out) + l * o_leaf;
-        HIP_TRY(launch_read(g, p, sc.part, s, l == 0 ? eb : nullptr, l + 1 == t.leaves ? ee : nullptr));
+    lr->p = resolve_plan(g, want, db->num_cus);
+    lr->staged = leaf_staging_supported(g, lr->p, t.leaves) &&
+                 m4rw_staging_bytes(g, lr->p) * t.leaves <= PREP_STAGE_MAX;
+    lr->q_leaf = lr->staged ? m4rw_staging_bytes(g, lr->p) : l.q_leaf;
+    // one launch for every leaf: the leaves' answers are consecutive row
+    // blocks of Bq rows
+    const uint64_t split_bytes = lr->p.splits <= 1 ? 0 : (uint64_t)lr->p.splits * l.Bq * l.Cq;
+    lr->fused = lr->staged && split_bytes * t.leaves <= PREP_PARTIAL_MAX;
+    lr->o_leaf = lr->fused ? (uint64_t)l.Bq * l.Cq : l.o_leaf;
+    PIR_TRY(ensure_device(&sc.leaf_q, &sc.leaf_q_cap, lr->q_leaf * t.leaves));
+    PIR_TRY(ensure_device(&sc.leaf_out, &sc.leaf_out_cap, lr->o_leaf * t.leaves));
+    if (lr->staged)
+        HIP_TRY(launch_stage_leaf_pairs(t, q, qp, B, db->n, g, lr->p, sc.leaf_q, lr->q_leaf, s));
+    else
+        HIP_TRY(launch_prep_q(t, q, qp, B, db->n, l.Bq, l.Wq, sc.leaf_q, l.qpl, l.q_leaf, s));
+    return PIR_OK;
+}
+
+// Preprocessed read of B rows, whose request side prep_requests enqueued on
+// stream s, into out (pitch op): the 7^L leaf products with the
+// Four-Russians kernels (one launch for all of them when their offsets are
+// staged), then the answers from the products (masked in place when keys are
+// given). `done` is recorded by the last kernel; eb / ee take the start of
+// the first leaf's main kernel and the end of the last one's.
+static int prep_read(pir_db *db, Scratch &sc, const LeafRead &lr, uint32_t B, void *out, uint64_t op,
+                     const uint32_t *keys, hipStream_t s, hipEvent_t eb, hipEvent_t ee, hipEvent_t done)
+{
+    const PrepTables &t = db->prep_t;
+    ReadGeom g = lr.g;
+    if (lr.staged)
+        g.staged = static_cast<const uint32_t *>(sc.leaf_q);
+    if (lr.fused) {
+        g.leaves = t.leaves;
+        g.leaf_d_bytes = db->prep_leaf_bytes;
+        g.leaf_stage_bytes = lr.q_leaf;
+        g.D = db->prep;
+        g.out = sc.leaf_out;
+        PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, lr.p)));
+        HIP_TRY(launch_read(g, lr.p, sc.part, s, eb, ee));
+    } else {
+        PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, lr.p)));
+        for (uint32_t l = 0; l < t.leaves; ++l) {
+            g.D = db->prep + l * db->prep_leaf_bytes;
+            uint8_t *lq = static_cast<uint8_t *>(sc.leaf_q) + l * lr.q_leaf;
+            if (lr.staged)
+                g.staged = reinterpret_cast<const uint32_t *>(lq);
+            else
+                g.Q = lq;
+            g.out = static_cast<uint8_t *>(sc.leaf_out) + l * lr.o_leaf;
+            HIP_TRY(launch_read(g, lr.p, sc.part, s, l == 0 ? eb : nullptr, l + 1 == t.leaves ? ee : nullptr));
+        }
     }
-    HIP_TRY(launch_prep_out(t, sc.leaf_out, o_leaf, B, Bq, Cq, out, op, s, keys ? nullptr : done));
+    HIP_TRY(launch_prep_out(t, sc.leaf_out, lr.o_leaf, B, lr.l.Bq, lr.l.Cq, out, op, s, keys ? nullptr : done));
     if (keys)
         HIP_TRY(launch_mask_rows(nullptr, 0, B, db->stride, out, op, keys, s, done));
     return PIR_OK;
@@ -824,8 +873,9 @@ static int read_sync(pir_db *db, const uint8_t *req_bits, uint32_t B, const uint
     hipEvent_t eb, ee;
     PIR_TRY(profile_slot(db, &eb, &ee));
     if (use_prep(db, B)) {
-        PIR_TRY(prep_requests(db, sc, sc.req, qp, B, db->stream));
-        PIR_TRY(prep_read(db, sc, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
+        LeafRead lr;
+        PIR_TRY(prep_requests(db, sc, sc.req, qp, B, db->stream, &lr));
+        PIR_TRY(prep_read(db, sc, lr, B, sc.resp, db->stride, g.keys, db->stream, eb, ee, nullptr));
     } else {
         Plan p = choose_plan(db, B);
         PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));
@@ -864,8 +914,9 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     // work that needs only the requests goes out before the wait for the
     // latest publication
     const bool prep = use_prep(db, B);
+    LeafRead lr;
     if (prep)
-        PIR_TRY(prep_requests(db, sc, q, qp, B, s));
+        PIR_TRY(prep_requests(db, sc, q, qp, B, s, &lr));
     PIR_TRY(wait_published(db, s));
     const bool direct = !(reinterpret_cast<uintptr_t>(d_resp) & 15) && !(resp_pitch & 15) &&
                         db->stride == db->bucket_bytes;
@@ -882,7 +933,7 @@ static int read_async(pir_db *db, const void *d_req, uint64_t req_pitch, uint32_
     PIR_TRY(profile_slot(db, &eb, &ee));
     PIR_TRY(reader_event(db, prep ? 2 : db->front, s, &done));
     if (prep) {
-        PIR_TRY(prep_read(db, sc, B, out, op, g.keys, s, eb, ee, direct ? done : nullptr));
+        PIR_TRY(prep_read(db, sc, lr, B, out, op, g.keys, s, eb, ee, direct ? done : nullptr));
     } else {
         Plan p = choose_plan(db, B);
         PIR_TRY(ensure_device(&sc.part, &sc.part_cap, partial_bytes(g, p)));

@@ -46,10 +46,10 @@ bool plan_supported(const Plan &p)
 
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
 {
-    uint64_t bytes = p.splits <= 1 ? 0 : (uint64_t)p.splits * g.B * g.stride;
+    uint64_t bytes = p.splits <= 1 ? 0 : (uint64_t)p.splits * g.leaves * g.B * g.stride;
     if (p.kind == KIND_M4R)
         bytes += m4r_staging_bytes(g);
-    if (p.kind == KIND_M4RW)
+    if (p.kind == KIND_M4RW && !(g.staged && (p.flags & PLAN_PAIRS)))
         bytes += m4rw_staging_bytes(g, p);
     return bytes;
 }
@@ -157,6 +157,8 @@ hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStre
 {
     if (g.B == 0)
         return hipSuccess;
+    if (g.leaves != 1 && !(g.leaves > 1 && g.staged && p.kind == KIND_M4RW && (p.flags & PLAN_PAIRS)))
+        return hipErrorInvalidValue;
     hipError_t e;
     if (p.kind == KIND_M4R)
         e = launch_m4r_read(g, p, partials, stream, ev_begin, ev_end);
@@ -167,7 +169,7 @@ hipError_t launch_read(const ReadGeom &g, const Plan &p, void *partials, hipStre
     // without splits the kernel wrote the plain answers: mask them in place
     if (e == hipSuccess && p.splits <= 1) {
         if (g.keys)
-            e = launch_mask_rows(nullptr, 0, g.B, g.stride, g.out, g.out_pitch, g.keys, stream, g.done);
+            e = launch_mask_rows(nullptr, 0, g.leaves * g.B, g.stride, g.out, g.out_pitch, g.keys, stream, g.done);
         else if (g.done)
             e = hipEventRecord(g.done, stream);
     }

@@ -43,6 +43,11 @@ struct WideArgs {
     uint64_t out_split16;
     uint64_t groups;        // ceil(n / 6)
     uint32_t n_rt, splits, groups_per_split, tasks_per_xcd;
+    // pair-table kernel: products of `leaves` databases of one shape in one
+    // launch, leaf l's at D + l * leaf_d_bytes, offsets at Qs + l * leaf_qs,
+    // answers l * leaf_out16 uint4 into each split's (or the final) rows
+    uint32_t leaves, tasks;
+    uint64_t leaf_d_bytes, leaf_qs, leaf_out16;
 };
 
 template <int NW>
@@ -221,7 +226,7 @@ void xorpir_m4rw_kernel(const WideArgs a)
     __shared__ uint4 lds[2 * TABLE_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
-    if (t >= a.n_rt * a.slices * a.splits)
+    if (t >= a.tasks)
         return;
     const uint32_t rt = t % a.n_rt;
     const uint32_t rest = t / a.n_rt;
@@ -457,12 +462,15 @@ void xorpir_m4rp_kernel(const WideArgs a)
     __shared__ uint4 lds[2 * S::SET_U4];
     const uint32_t L = blockIdx.x;
     const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
-    if (t >= a.n_rt * a.slices * a.splits)
+    if (t >= a.tasks)
         return;
     const uint32_t rt = t % a.n_rt;
     const uint32_t rest = t / a.n_rt;
     const uint32_t slice = rest % a.slices;
-    const uint32_t s = rest / a.slices;
+    const uint32_t rest2 = rest / a.slices;
+    const uint32_t s = rest2 % a.splits;
+    const uint32_t leaf = rest2 / a.splits;
+    const uint8_t *D = a.D + leaf * a.leaf_d_bytes;
 
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t half = wave / (NW / 2), wt = wave % (NW / 2);
@@ -485,8 +493,8 @@ void xorpir_m4rp_kernel(const WideArgs a)
         uint4 ring[P][G];
 #pragma unroll
         for (int k = 0; k < P; ++k)
-            load_half<G>(ring[k], a.D, a.row_bytes, lane_off, gb + k, half);
-        const uint32_t *Qw = a.Qs + r0;
+            load_half<G>(ring[k], D, a.row_bytes, lane_off, gb + k, half);
+        const uint32_t *Qw = a.Qs + leaf * a.leaf_qs + r0;
         uint32_t offs[TW] = {};
         if (active) {
 #pragma unroll
@@ -497,15 +505,15 @@ void xorpir_m4rp_kernel(const WideArgs a)
         __syncthreads();
         uint64_t y = gb;
         for (; y + U <= ge; y += U)
-            pair_steps<NW, TW, P, 0, U, G>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, Qw, a.Bp, active,
+            pair_steps<NW, TW, P, 0, U, G>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, Qw, a.Bp, active,
                                            half, wt, lane);
         if (y < ge)
-            pair_steps_tail<NW, TW, P, 0, U, G>(acc, ring, offs, lds, a.D, a.row_bytes, lane_off, y, ge - y, Qw,
+            pair_steps_tail<NW, TW, P, 0, U, G>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, ge - y, Qw,
                                                 a.Bp, active, half, wt, lane);
     }
 
     if (active && col_ok) {
-        uint4 *o = reinterpret_cast<uint4 *>(a.out) + (uint64_t)s * a.out_split16 + col;
+        uint4 *o = reinterpret_cast<uint4 *>(a.out) + leaf * a.leaf_out16 + (uint64_t)s * a.out_split16 + col;
 #pragma unroll
         for (int r = 0; r < TW; ++r)
             if (r0 + r < a.B)
@@ -523,6 +531,32 @@ void xorpir_m4rp_kernel(const WideArgs a)
 // at an odd word stride, and each wave then writes a pair's 64 offsets per
 // store, one row per lane.
 constexpr int PAIR_CHUNK = 64;
+
+// The offsets of chunk steps y0 .. y0 + PAIR_CHUNK - 1 (none past `pairs`)
+// of rows r0 .. r0 + 63 from their request bits in LDS (a row per RS-word
+// stride, the chunk's last window padded with a zero word).
+template <int G, bool NT = false>
+__device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_t y0, uint64_t pairs,
+                                                   uint32_t *__restrict__ Qs, uint32_t Bp, uint32_t r0)
+{
+    using S = PairShape<G>;
+    constexpr int RS = PAIR_CHUNK * S::BUCKETS / 32 + 1;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t k = wave; k < PAIR_CHUNK; k += 4) {
+        const uint64_t y = y0 + k;
+        if (y > pairs)
+            break;
+        const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
+        const uint64_t win = (uint64_t)bits[lane * RS + j] | ((uint64_t)bits[lane * RS + j + 1] << 32);
+        const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
+        const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
+        const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
+        if constexpr (NT)
+            __builtin_nontemporal_store((tb << 16) | ta, Qs + y * Bp + r0 + lane);
+        else
+            Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
+    }
+}
 
 template <int G>
 __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
@@ -556,19 +590,71 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
     if (t < 64)
         bits[t * RS + W] = 0u;  // the high word of the chunk's last window
     __syncthreads();
-    const uint32_t wave = t >> 6, lane = t & 63u;
-    const uint64_t y0 = (uint64_t)blockIdx.x * PAIR_CHUNK;
-    for (uint32_t k = wave; k < PAIR_CHUNK; k += 4) {
-        const uint64_t y = y0 + k;
-        if (y > pairs)
-            break;
-        const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
-        const uint64_t win = (uint64_t)bits[lane * RS + j] | ((uint64_t)bits[lane * RS + j + 1] << 32);
-        const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
-        const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
-        const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
-        Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
+    write_pair_offsets<G>(bits, (uint64_t)blockIdx.x * PAIR_CHUNK, pairs, Qs, Bp, r0);
+}
+
+// Pair offsets of every leaf of a preprocessed read, staged straight from
+// the request rows. Leaf l's row r is the XOR of the request blocks that
+// t.a[l] names (row block blk >> 4: rows (blk >> 4) * Bq + r; column block
+// blk & 15: bits (blk & 15) * Nq .. + Nq, bits >= n read as zero), and its
+// offsets are the ones stage_pair_offsets_kernel stages from that row, at
+// Qs + l * leaf_w. One launch for all leaves stands in for forming the leaf
+// rows and staging every leaf in a launch of its own. blockIdx: x = 64 rows
+// (the workgroups of one leaf and chunk run side by side and fill its pairs'
+// offset rows together), y = leaf (the leaves that share request blocks
+// follow each other), z = chunk.
+template <int G>
+__global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const PrepTables tb, const uint32_t *__restrict__ Q,
+                                                               uint64_t qpitch_w, uint32_t B, uint64_t n, uint32_t Bq,
+                                                               uint64_t Wq, uint32_t *__restrict__ Qs, uint64_t leaf_w,
+                                                               uint32_t Bp, uint64_t pairs)
+{
+    using S = PairShape<G>;
+    constexpr int W = PAIR_CHUNK * S::BUCKETS / 32;
+    constexpr int RS = W + 1;
+    __shared__ uint32_t bits[64 * RS];
+    const uint32_t t = threadIdx.x;
+    const uint32_t leaf = blockIdx.y;
+    const uint32_t r0 = blockIdx.x * 64;
+    const uint64_t w0 = (uint64_t)blockIdx.z * W;
+    const int cnt = tb.a_cnt[leaf];
+    // Every thread's words of every request block are loaded before any is
+    // used, so 4 x KW loads are in flight per thread: a word outside the
+    // rows, the bits or the leaf's count of blocks is loaded from word 0 of
+    // the requests (always present) and masked to zero.
+    constexpr int KW = (64 * W + 255) / 256;
+    uint32_t blk[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        blk[e] = tb.a[leaf][e < cnt ? e : 0];
+    uint32_t got[4][KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const uint32_t i = t + 256u * k;
+        const uint32_t row = i / W, w = i % W;
+        const uint32_t lr = r0 + row;
+        const uint64_t wi = w0 + w;
+        const bool in = i < 64u * W && lr < Bq && wi < Wq;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint64_t r = (uint64_t)(blk[e] >> 4) * Bq + lr;
+            const uint64_t sw = (blk[e] & 15u) * Wq + wi;
+            const uint64_t bit = sw * 32;
+            const bool ok = in && e < cnt && r < B && bit < n;
+            const uint32_t keep = !ok ? 0u : bit + 32 > n ? (1u << (n - bit)) - 1u : ~0u;
+            got[e][k] = Q[ok ? r * qpitch_w + sw : 0] & keep;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const uint32_t i = t + 256u * k;
+        if (i < 64u * W)
+            bits[(i / W) * RS + i % W] = got[0][k] ^ got[1][k] ^ got[2][k] ^ got[3][k];
+    }
+    if (t < 64)
+        bits[t * RS + W] = 0u;
+    __syncthreads();
+    write_pair_offsets<G, true>(bits, (uint64_t)blockIdx.z * PAIR_CHUNK, pairs, Qs + leaf * leaf_w, Bp, r0);
 }
 
 // Qs[g * Bp + r] = (bits 6g .. 6g+5 of request row r, bits >= n cleared) *
@@ -702,6 +788,30 @@ uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p)
     return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * 4 + 255) & ~255ull;
 }
 
+bool leaf_staging_supported(const ReadGeom &g, const Plan &p, uint32_t leaves)
+{
+    if (p.kind != KIND_M4RW || !plan_pairs(p) || !m4rw_plan_supported(p) || g.n % 32)
+        return false;
+    const uint64_t chunks = (m4rw_steps(g.n, p) + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
+    return chunks <= 65535 && leaves >= 1 && leaves <= PREP_MAX_LEAVES;
+}
+
+hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n,
+                                   const ReadGeom &g, const Plan &p, void *staged, uint64_t leaf_bytes,
+                                   hipStream_t stream)
+{
+    if (!leaf_staging_supported(g, p, t.leaves) || (leaf_bytes & 3) || (qpitch & 3))
+        return hipErrorInvalidValue;
+    const uint64_t pairs = m4rw_steps(g.n, p);
+    const uint32_t chunks = (uint32_t)((pairs + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK);
+    const uint32_t Bp = padded_rows(g.B);
+    const uint32_t G = plan_pair_g(p);
+    auto k = G == 5 ? stage_leaf_pairs_kernel<5> : G == 4 ? stage_leaf_pairs_kernel<4> : stage_leaf_pairs_kernel<3>;
+    hipLaunchKernelGGL(k, dim3(Bp / 64, t.leaves, chunks), dim3(256), 0, stream, t, static_cast<const uint32_t *>(Q),
+                       qpitch / 4, B, n, g.B, g.n / 32, static_cast<uint32_t *>(staged), leaf_bytes / 4, Bp, pairs);
+    return hipGetLastError();
+}
+
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
 {
     const uint32_t stride16 = (uint32_t)(g.stride / 16);
@@ -725,7 +835,9 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.Bp = padded_rows(g.B);
     a.groups = m4rw_steps(g.n, p);
     uint32_t *qs = static_cast<uint32_t *>(partials);
-    {
+    if (g.staged && plan_pairs(p)) {
+        qs = const_cast<uint32_t *>(g.staged);
+    } else {
         if (plan_pairs(p)) {
             const uint64_t chunks = (a.groups + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK;
             if (chunks * 256 > 0xffffffffull)  // a grid dimension holds fewer than 2^32 work-items
@@ -748,27 +860,40 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
             return e;
     }
     a.Qs = qs;
-    partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g, p);
+    if (!(g.staged && plan_pairs(p)))
+        partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g, p);
     const uint32_t R = p.tile * p.unroll;
     a.n_rt = (g.B + R - 1) / R;
     a.splits = p.splits;
     a.groups_per_split = (uint32_t)((a.groups + p.splits - 1) / p.splits);
+    // leaves > 1: the leaves' answers are rows l * B + r of one [leaves * B]
+    // row block, split by split, so one reduction serves them all
+    a.leaves = g.leaves;
+    a.leaf_d_bytes = g.leaf_d_bytes;
+    a.leaf_qs = g.leaf_stage_bytes / 4;
     if (p.splits > 1) {
         a.out = static_cast<uint32_t *>(partials);
         a.out_row16 = a.stride16;
-        a.out_split16 = (uint64_t)g.B * a.stride16;
+        a.leaf_out16 = (uint64_t)g.B * a.stride16;
+        a.out_split16 = (uint64_t)g.leaves * g.B * a.stride16;
     } else {
         a.out = static_cast<uint32_t *>(g.out);
         a.out_row16 = g.out_pitch / 16;
+        a.leaf_out16 = (uint64_t)g.B * a.out_row16;
         a.out_split16 = 0;
     }
-    const uint64_t tasks = (uint64_t)a.n_rt * a.slices * a.splits;
+    const uint64_t tasks = (uint64_t)a.n_rt * a.slices * a.splits * g.leaves;
+    if ((tasks + 7) / 8 * 8 * p.unroll * 64 > 0xffffffffull)  // a launch holds fewer than 2^32 work-items
+        return hipErrorInvalidValue;
+    a.tasks = (uint32_t)tasks;
     a.tasks_per_xcd = (uint32_t)((tasks + 7) / 8);
     hipExtLaunchKernelGGL(fn, dim3(a.tasks_per_xcd * 8), dim3(p.unroll * 64), 0, stream, eb, ee, 0, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.splits <= 1)
         return e;
-    return launch_split_reduce(partials, p.splits, g, stream);
+    ReadGeom all = g;
+    all.B = g.leaves * g.B;
+    return launch_split_reduce(partials, p.splits, all, stream);
 }
 
 }  // namespace talek

@@ -42,6 +42,46 @@ def test_preprocessed_reads_match_oracle(levels, n, d, z):
             assert_rows_equal(out.cpu().numpy(), want, f"L={levels} B={B} async")
 
 
+_P = pir.PLAN_PAIRS
+LEAF_PLANS = [(pir.KERNEL_M4R_WIDE, 32, 0, 8, _P), (pir.KERNEL_M4R_WIDE, 32, 3, 4, _P),
+              (pir.KERNEL_M4R_WIDE, 16, 0, 8, _P | 4 << 8), (pir.KERNEL_M4R_WIDE, 8, 5, 8, _P | pir.PLAN_PAIR_G4),
+              (pir.KERNEL_M4R_WIDE, 4, 0, 8, _P | pir.PLAN_PAIR_G3), (pir.KERNEL_M4R_WIDE, 8, 1, 8, _P | 4 << 8),
+              (pir.KERNEL_M4R_WIDE, 16, 0, 8, pir.PLAN_ROLLING),
+              (pir.KERNEL_MASK, 4, 0, 8, 0)]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_leaf_reads_under_every_plan_family(levels):
+    """Leaf reads under forced plans: the pair-table plans (offsets of every
+    leaf staged in one launch from the request rows, every leaf answered by
+    one launch) with 5-, 4- and 3-bucket tables, with and without splits and
+    with ragged request tiles, and plans that read formed leaf request rows
+    instead (rolling tables, masked XOR); ragged n and B, synchronous and
+    async reads with unaligned request rows, all bit-exact against the
+    oracle."""
+    import torch
+    n, d, z = 2000, 2, 512
+    D = synth.uniform_db(960 + levels, n, d * z)
+    reqs = {B: synth.bernoulli_requests(970 + B, B, n) for B in (5, 97, 600)}
+    want = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=1)
+        for plan in LEAF_PLANS:
+            db.set_plan(*plan)
+            for B, req in reqs.items():
+                assert_rows_equal(db.read(req), want[B], f"L={levels} plan={plan} B={B} sync")
+            B = 97
+            qb = reqs[B].shape[1]
+            buf = torch.zeros((B, qb + 3), dtype=torch.uint8, device="cuda")
+            buf[:, 1:1 + qb] = torch.from_numpy(reqs[B]).cuda()
+            out = torch.zeros((B, d * z), dtype=torch.uint8, device="cuda")
+            db.read_async(buf[:, 1:1 + qb], out)
+            torch.cuda.synchronize()
+            assert_rows_equal(out.cpu().numpy(), want[B], f"L={levels} plan={plan} B={B} async, unaligned rows")
+        db.set_plan()
+
+
 @pytest.mark.parametrize("levels", [1, 2])
 def test_preprocessed_reads_follow_epochs_and_masks(levels):
     """Commits that change the snapshot rebuild the leaves: reads after each
