@@ -172,10 +172,11 @@ struct PrepTables {
 };
 bool prep_tables(uint32_t levels, PrepTables *t);
 // Whether launch_stage_leaf_pairs serves leaf reads of geometry g (n, B, the
-// leaf's) under plan p, and the bytes it stages per leaf.
+// leaf's) under plan p, and the bytes a read of geometry g stages (32-bit
+// entries, or the 16-bit entries of staged leaves when half).
 bool leaf_staging_supported(const ReadGeom &g, const Plan &p, uint32_t leaves);
-uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p);
-// The pair-table offsets of every leaf's request rows (leaf i at
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p, bool half);
+// The pair-table entries (16-bit) of every leaf's request rows (leaf i at
 // staged + i * leaf_bytes), staged from the B request rows Q (pitch qpitch
 // bytes, 4-byte aligned, n bits) of a read.
 hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t qpitch, uint32_t B, uint64_t n,

@@ -782,8 +782,8 @@ static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, ui
     }
     lr->p = resolve_plan(g, want, db->num_cus);
     lr->staged = leaf_staging_supported(g, lr->p, t.leaves) &&
-                 m4rw_staging_bytes(g, lr->p) * t.leaves <= PREP_STAGE_MAX;
-    lr->q_leaf = lr->staged ? m4rw_staging_bytes(g, lr->p) : l.q_leaf;
+                 m4rw_staging_bytes(g, lr->p, true) * t.leaves <= PREP_STAGE_MAX;
+    lr->q_leaf = lr->staged ? m4rw_staging_bytes(g, lr->p, true) : l.q_leaf;
     // one launch for every leaf: the leaves' answers are consecutive row
     // blocks of Bq rows
     const uint64_t split_bytes = lr->p.splits <= 1 ? 0 : (uint64_t)lr->p.splits * l.Bq * l.Cq;

@@ -17,7 +17,7 @@ bool m4rw_plan_supported(const Plan &p);
 hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
                             hipEvent_t ee);
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p);
-uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p);
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p, bool half);
 uint64_t m4rw_steps(uint64_t n, const Plan &p);
 
 namespace {
@@ -50,7 +50,7 @@ uint64_t partial_bytes(const ReadGeom &g, const Plan &p)
     if (p.kind == KIND_M4R)
         bytes += m4r_staging_bytes(g);
     if (p.kind == KIND_M4RW && !(g.staged && (p.flags & PLAN_PAIRS)))
-        bytes += m4rw_staging_bytes(g, p);
+        bytes += m4rw_staging_bytes(g, p, false);
     return bytes;
 }
 

@@ -354,25 +354,57 @@ __device__ __forceinline__ void xor3x4(uint4 &a, const uint4 &b, const uint4 &c)
     a.w = xor3(a.w, b.w, c.w);
 }
 
-// Rolling pair lookups: off[r] holds table A's byte offset in its low half
-// and table B's (set-relative, so including the 32 KiB of table A) in its
-// high half.
-template <int TW, int INFL>
-__device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *set, const uint32_t (&off)[TW])
+// Rolling pair lookups. Two forms of the staged request bits:
+// H = false: off[r] holds table A's byte offset in its low half and table
+// B's (set-relative, so including table A's 2^G KiB) in its high half.
+// H = true: off[r / 2] holds the 2G request bits of rows r (even r in its low
+// half, odd r in its high half; table A's G bits lowest); an entry is
+// ENTRY_BYTES = 2^10 bytes, so each offset is one shift and one AND of the
+// word (a scalar op more per offset than the first form, for half the
+// staged bytes).
+template <int G, int TW, bool H>
+__device__ __forceinline__ uint32_t pair_off_a(const uint32_t (&off)[H ? TW / 2 : TW], int r)
 {
+    if constexpr (H) {
+        constexpr uint32_t M = (uint32_t)((1 << G) - 1) * ENTRY_BYTES;
+        const uint32_t w = off[r >> 1];
+        return (r & 1) ? (w >> 6) & M : (w << 10) & M;
+    } else {
+        return off[r] & 0xffffu;
+    }
+}
+
+template <int G, int TW, bool H>
+__device__ __forceinline__ uint32_t pair_off_b(const uint32_t (&off)[H ? TW / 2 : TW], int r)
+{
+    if constexpr (H) {
+        constexpr uint32_t M = (uint32_t)((1 << G) - 1) * ENTRY_BYTES;
+        constexpr uint32_t TB = (uint32_t)(1 << G) * ENTRY_BYTES;  // table B follows table A in the set
+        const uint32_t w = off[r >> 1];
+        return TB + ((r & 1) ? (w >> (6 + G)) & M : (w << (10 - G)) & M);
+    } else {
+        return off[r] >> 16;
+    }
+}
+
+template <int G, int TW, int INFL, bool H>
+__device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *set,
+                                             const uint32_t (&off)[H ? TW / 2 : TW])
+{
+    static_assert(ENTRY_BYTES == 1 << 10 && G <= 5 && TW % 2 == 0, "offsets below 64 KiB");
     uint4 ta[INFL], tb[INFL];
 #pragma unroll
     for (int i = 0; i < INFL; ++i) {
-        ta[i] = *reinterpret_cast<const uint4 *>(set + (off[i] & 0xffffu));
-        tb[i] = *reinterpret_cast<const uint4 *>(set + (off[i] >> 16));
+        ta[i] = *reinterpret_cast<const uint4 *>(set + pair_off_a<G, TW, H>(off, i));
+        tb[i] = *reinterpret_cast<const uint4 *>(set + pair_off_b<G, TW, H>(off, i));
     }
 #pragma unroll
     for (int r = 0; r < TW; ++r) {
         __builtin_amdgcn_sched_barrier(0);
         xor3x4(acc[r], ta[r % INFL], tb[r % INFL]);
         if (r + INFL < TW) {
-            ta[r % INFL] = *reinterpret_cast<const uint4 *>(set + (off[r + INFL] & 0xffffu));
-            tb[r % INFL] = *reinterpret_cast<const uint4 *>(set + (off[r + INFL] >> 16));
+            ta[r % INFL] = *reinterpret_cast<const uint4 *>(set + pair_off_a<G, TW, H>(off, r + INFL));
+            tb[r % INFL] = *reinterpret_cast<const uint4 *>(set + pair_off_b<G, TW, H>(off, r + INFL));
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -383,11 +415,12 @@ __device__ __forceinline__ void lookup_pairs(uint4 (&acc)[TW], const uint8_t *se
 // pair y is looked up; the next pair's offsets are fetched; the half of pair
 // y + 1 in ring[(K + 1) % P] is built into the other set (before the lookups
 // for the shapes named below); barrier.
-template <int NW, int TW, int P, int K, int G>
-__device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW],
+template <int NW, int TW, int P, int K, int G, bool H>
+__device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
+                                          uint32_t (&offs)[H ? TW / 2 : TW],
                                           uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
                                           uint32_t lane_off, uint64_t y, const uint32_t *__restrict__ Qw,
-                                          uint32_t Bp, bool active, uint32_t half, uint32_t wt, uint32_t lane)
+                                          uint32_t Bw, bool active, uint32_t half, uint32_t wt, uint32_t lane)
 {
     using S = PairShape<G>;
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
@@ -403,15 +436,16 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
     if (!late_build)
         build_half<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
     if (active) {
-        lookup_pairs<TW, in_flight>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane), offs);
-        // the next pair's offsets (rows r0 .. r0 + TW - 1 < Bp of pair
-        // y + 1 <= pairs, inside the staging area); the index goes through
-        // readfirstlane for the reason given in group_step
+        lookup_pairs<G, TW, in_flight, H>(acc, reinterpret_cast<const uint8_t *>(lds + buf * S::SET_U4 + lane),
+                                          offs);
+        // the next pair's staged words (rows r0 .. r0 + TW - 1 < Bp of pair
+        // y + 1 <= pairs, Bw words a pair, inside the staging area); the
+        // index goes through readfirstlane for the reason given in group_step
         const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(y + 1));
         const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((y + 1) >> 32));
-        const uint32_t *qn = Qw + (((uint64_t)hi << 32) | lo) * Bp;
+        const uint32_t *qn = Qw + (((uint64_t)hi << 32) | lo) * Bw;
 #pragma unroll
-        for (int i = 0; i < TW; ++i)
+        for (int i = 0; i < (H ? TW / 2 : TW); ++i)
             offs[i] = qn[i];
     }
     if (late_build)
@@ -419,22 +453,24 @@ __device__ __forceinline__ void pair_step(uint4 (&acc)[TW], uint4 (&ring)[P][G],
     __syncthreads();
 }
 
-template <int NW, int TW, int P, int K, int U, int G>
-__device__ __forceinline__ void pair_steps(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW], uint4 *lds,
+template <int NW, int TW, int P, int K, int U, int G, bool H>
+__device__ __forceinline__ void pair_steps(uint4 (&acc)[TW], uint4 (&ring)[P][G],
+                                           uint32_t (&offs)[H ? TW / 2 : TW], uint4 *lds,
                                            const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
                                            uint64_t y, const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
                                            uint32_t half, uint32_t wt, uint32_t lane)
 {
     if constexpr (K < U) {
-        pair_step<NW, TW, P, K, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half, wt,
-                                   lane);
-        pair_steps<NW, TW, P, K + 1, U, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y, Qw, Bp, active, half, wt,
-                                           lane);
+        pair_step<NW, TW, P, K, G, H>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half,
+                                      wt, lane);
+        pair_steps<NW, TW, P, K + 1, U, G, H>(acc, ring, offs, lds, D, row_bytes, lane_off, y, Qw, Bp, active, half,
+                                              wt, lane);
     }
 }
 
-template <int NW, int TW, int P, int K, int U, int G>
-__device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][G], uint32_t (&offs)[TW],
+template <int NW, int TW, int P, int K, int U, int G, bool H>
+__device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[P][G],
+                                                uint32_t (&offs)[H ? TW / 2 : TW],
                                                 uint4 *lds, const uint8_t *__restrict__ D, uint64_t row_bytes,
                                                 uint32_t lane_off, uint64_t y, uint64_t left,
                                                 const uint32_t *__restrict__ Qw, uint32_t Bp, bool active,
@@ -442,16 +478,18 @@ __device__ __forceinline__ void pair_steps_tail(uint4 (&acc)[TW], uint4 (&ring)[
 {
     if constexpr (K < U) {
         if ((uint64_t)K < left) {
-            pair_step<NW, TW, P, K, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active, half,
-                                       wt, lane);
-            pair_steps_tail<NW, TW, P, K + 1, U, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw, Bp,
-                                                    active, half, wt, lane);
+            pair_step<NW, TW, P, K, G, H>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bp, active,
+                                          half, wt, lane);
+            pair_steps_tail<NW, TW, P, K + 1, U, G, H>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw,
+                                                       Bp, active, half, wt, lane);
         }
     }
 }
 
 // Same task layout and outputs as xorpir_m4rw_kernel; a.groups counts pairs.
-template <int NW, int TW, int P, int G>
+// H: the staged request bits are 16-bit entries (launch_stage_leaf_pairs),
+// else 32-bit offset pairs (stage_pair_offsets_kernel).
+template <int NW, int TW, int P, int G, bool H>
 __global__ __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(NW / 4 * PairShape<G>::WGS, NW / 4 * PairShape<G>::WGS)))
 void xorpir_m4rp_kernel(const WideArgs a)
@@ -494,22 +532,25 @@ void xorpir_m4rp_kernel(const WideArgs a)
 #pragma unroll
         for (int k = 0; k < P; ++k)
             load_half<G>(ring[k], D, a.row_bytes, lane_off, gb + k, half);
-        const uint32_t *Qw = a.Qs + leaf * a.leaf_qs + r0;
-        uint32_t offs[TW] = {};
+        // staged words: two rows a word with 16-bit entries (r0 is even)
+        constexpr int OW = H ? TW / 2 : TW;
+        const uint32_t Bw = H ? a.Bp / 2 : a.Bp;
+        const uint32_t *Qw = a.Qs + leaf * a.leaf_qs + (H ? r0 / 2 : r0);
+        uint32_t offs[OW] = {};
         if (active) {
 #pragma unroll
-            for (int i = 0; i < TW; ++i)
-                offs[i] = Qw[gb * a.Bp + i];
+            for (int i = 0; i < OW; ++i)
+                offs[i] = Qw[gb * Bw + i];
         }
         build_half<NW / 2, G>(lds + half * S::TABLE_U4, ring[0], wt, lane);
         __syncthreads();
         uint64_t y = gb;
         for (; y + U <= ge; y += U)
-            pair_steps<NW, TW, P, 0, U, G>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, Qw, a.Bp, active,
+            pair_steps<NW, TW, P, 0, U, G, H>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, Qw, Bw, active,
                                            half, wt, lane);
         if (y < ge)
-            pair_steps_tail<NW, TW, P, 0, U, G>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, ge - y, Qw,
-                                                a.Bp, active, half, wt, lane);
+            pair_steps_tail<NW, TW, P, 0, U, G, H>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, ge - y, Qw,
+                                                Bw, active, half, wt, lane);
     }
 
     if (active && col_ok) {
@@ -521,21 +562,21 @@ void xorpir_m4rp_kernel(const WideArgs a)
     }
 }
 
-// Qs[y * Bp + r] = (B << 16) | A: for pair y and request row r, with a / b
-// the G request bits of tables A / B (bits >= n cleared), the low half holds
-// a * 1024 and the high half b * 1024 + 2^G KiB (table B's offset within the
-// set; below 64 KiB for G <= 5). Rows B <= r < Bp and the extra pair y = pairs
-// hold zero bits. A workgroup covers 64 rows and PAIR_CHUNK pairs, whose
+// Qs[y * Bp + r] for pair y and request row r, with a / b the G request bits
+// of tables A / B (bits >= n cleared): as 32-bit entries (B << 16) | A, A =
+// a * 1024 and B = b * 1024 + 2^G KiB (table B's offset within the set;
+// below 64 KiB for G <= 5); as 16-bit entries a | b << G. Rows B <= r < Bp
+// and the extra pair y = pairs hold zero bits. A workgroup covers 64 rows and PAIR_CHUNK pairs, whose
 // 2G * PAIR_CHUNK request bits are exactly 4G words of each row: it loads
 // them row by row (consecutive threads on consecutive words) into LDS, rows
 // at an odd word stride, and each wave then writes a pair's 64 offsets per
 // store, one row per lane.
 constexpr int PAIR_CHUNK = 64;
 
-// The offsets of chunk steps y0 .. y0 + PAIR_CHUNK - 1 (none past `pairs`)
-// of rows r0 .. r0 + 63 from their request bits in LDS (a row per RS-word
-// stride, the chunk's last window padded with a zero word).
-template <int G, bool NT = false>
+// The staged entries of chunk steps y0 .. y0 + PAIR_CHUNK - 1 (none past
+// `pairs`) of rows r0 .. r0 + 63 from their request bits in LDS (a row per
+// RS-word stride, the chunk's last window padded with a zero word).
+template <int G, bool H, bool NT = false>
 __device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_t y0, uint64_t pairs,
                                                    uint32_t *__restrict__ Qs, uint32_t Bp, uint32_t r0)
 {
@@ -549,12 +590,17 @@ __device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_
         const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
         const uint64_t win = (uint64_t)bits[lane * RS + j] | ((uint64_t)bits[lane * RS + j + 1] << 32);
         const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
-        const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
-        const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
-        if constexpr (NT)
-            __builtin_nontemporal_store((tb << 16) | ta, Qs + y * Bp + r0 + lane);
-        else
+        if constexpr (H) {
+            uint16_t *Qh = reinterpret_cast<uint16_t *>(Qs) + y * Bp + r0 + lane;
+            if constexpr (NT)
+                __builtin_nontemporal_store((uint16_t)v, Qh);
+            else
+                *Qh = (uint16_t)v;
+        } else {
+            const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
+            const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
             Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
+        }
     }
 }
 
@@ -590,21 +636,27 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
     if (t < 64)
         bits[t * RS + W] = 0u;  // the high word of the chunk's last window
     __syncthreads();
-    write_pair_offsets<G>(bits, (uint64_t)blockIdx.x * PAIR_CHUNK, pairs, Qs, Bp, r0);
+    write_pair_offsets<G, false>(bits, (uint64_t)blockIdx.x * PAIR_CHUNK, pairs, Qs, Bp, r0);
 }
 
-// Pair offsets of every leaf of a preprocessed read, staged straight from
-// the request rows. Leaf l's row r is the XOR of the request blocks that
-// t.a[l] names (row block blk >> 4: rows (blk >> 4) * Bq + r; column block
-// blk & 15: bits (blk & 15) * Nq .. + Nq, bits >= n read as zero), and its
-// offsets are the ones stage_pair_offsets_kernel stages from that row, at
-// Qs + l * leaf_w. One launch for all leaves stands in for forming the leaf
+// Pair entries (16-bit) of every leaf of a preprocessed read, staged
+// straight from the request rows. Leaf l's row r is the XOR of the request
+// blocks of its A-combination (lc.w[l]; block blk: row block blk >> 4, rows
+// (blk >> 4) * Bq + r; column block blk & 15, bits (blk & 15) * Nq .. + Nq,
+// bits >= n read as zero), and its entries are the ones
+// stage_pair_offsets_kernel would stage from that row, at Qs + l * leaf_w. One launch for all leaves stands in for forming the leaf
 // rows and staging every leaf in a launch of its own. blockIdx: x = 64 rows
 // (the workgroups of one leaf and chunk run side by side and fill its pairs'
 // offset rows together), y = leaf (the leaves that share request blocks
 // follow each other), z = chunk.
+// A leaf's request blocks packed in one word (so a workgroup fetches them
+// with one scalar load): bits 0-3 the count, then 6 bits per block.
+struct LeafCombos {
+    uint32_t w[PREP_MAX_LEAVES];
+};
+
 template <int G>
-__global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const PrepTables tb, const uint32_t *__restrict__ Q,
+__global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const LeafCombos lc, const uint32_t *__restrict__ Q,
                                                                uint64_t qpitch_w, uint32_t B, uint64_t n, uint32_t Bq,
                                                                uint64_t Wq, uint32_t *__restrict__ Qs, uint64_t leaf_w,
                                                                uint32_t Bp, uint64_t pairs)
@@ -617,7 +669,8 @@ __global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const PrepTables 
     const uint32_t leaf = blockIdx.y;
     const uint32_t r0 = blockIdx.x * 64;
     const uint64_t w0 = (uint64_t)blockIdx.z * W;
-    const int cnt = tb.a_cnt[leaf];
+    const uint32_t lw = lc.w[leaf];
+    const int cnt = lw & 15u;
     // Every thread's words of every request block are loaded before any is
     // used, so 4 x KW loads are in flight per thread: a word outside the
     // rows, the bits or the leaf's count of blocks is loaded from word 0 of
@@ -626,7 +679,7 @@ __global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const PrepTables 
     uint32_t blk[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-        blk[e] = tb.a[leaf][e < cnt ? e : 0];
+        blk[e] = (lw >> (4 + 6 * e)) & 63u;
     uint32_t got[4][KW];
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
@@ -654,7 +707,7 @@ __global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const PrepTables 
     if (t < 64)
         bits[t * RS + W] = 0u;
     __syncthreads();
-    write_pair_offsets<G, true>(bits, (uint64_t)blockIdx.z * PAIR_CHUNK, pairs, Qs + leaf * leaf_w, Bp, r0);
+    write_pair_offsets<G, true, true>(bits, (uint64_t)blockIdx.z * PAIR_CHUNK, pairs, Qs + leaf * leaf_w, Bp, r0);
 }
 
 // Qs[g * Bp + r] = (bits 6g .. 6g+5 of request row r, bits >= n cleared) *
@@ -725,33 +778,39 @@ WideFn wide_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t mode)
     return nullptr;
 }
 
-WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g)
+template <bool H>
+WideFn pair_fn_h(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g)
 {
     if (depth == 0)
         depth = 2;
     if (g == 5) {
-        if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<4, 16, 2, 5>;
-        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<4, 32, 2, 5>;
-        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 5>;
-        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 5>;
-        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 5>;
-        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 5>;
-        if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rp_kernel<8, 16, 4, 5>;
-        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<8, 32, 2, 5>;
-        if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rp_kernel<8, 32, 3, 5>;
+        if (nw == 4 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<4, 16, 2, 5, H>;
+        if (nw == 4 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<4, 32, 2, 5, H>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 5, H>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 5, H>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 5, H>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 5, H>;
+        if (nw == 8 && tw == 16 && depth == 4) return xorpir_m4rp_kernel<8, 16, 4, 5, H>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rp_kernel<8, 32, 2, 5, H>;
+        if (nw == 8 && tw == 32 && depth == 3) return xorpir_m4rp_kernel<8, 32, 3, 5, H>;
     } else if (g == 4) {
-        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 4>;
-        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 4>;
-        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 4>;
-        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 4>;
-        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 4>;
+        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 4, H>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 4, H>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 4, H>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 4, H>;
+        if (nw == 8 && tw == 16 && depth == 2) return xorpir_m4rp_kernel<8, 16, 2, 4, H>;
     } else if (g == 3) {
-        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 3>;
-        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 3>;
-        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 3>;
-        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 3>;
+        if (nw == 8 && tw == 4 && depth == 2) return xorpir_m4rp_kernel<8, 4, 2, 3, H>;
+        if (nw == 8 && tw == 4 && depth == 4) return xorpir_m4rp_kernel<8, 4, 4, 3, H>;
+        if (nw == 8 && tw == 8 && depth == 2) return xorpir_m4rp_kernel<8, 8, 2, 3, H>;
+        if (nw == 8 && tw == 8 && depth == 4) return xorpir_m4rp_kernel<8, 8, 4, 3, H>;
     }
     return nullptr;
+}
+
+WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g, bool half)
+{
+    return half ? pair_fn_h<true>(nw, tw, depth, g) : pair_fn_h<false>(nw, tw, depth, g);
 }
 
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
@@ -759,9 +818,9 @@ uint32_t plan_pair_g(const Plan &p) { return 5u - ((p.flags >> PLAN_PAIR_G_SHIFT
 uint32_t plan_mode(const Plan &p) { return (p.flags & PLAN_ROLLING) ? 1u : 0u; }
 bool plan_pairs(const Plan &p) { return (p.flags & PLAN_PAIRS) != 0; }
 
-WideFn plan_fn(const Plan &p)
+WideFn plan_fn(const Plan &p, bool half = false)
 {
-    return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p), plan_pair_g(p))
+    return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p), plan_pair_g(p), half)
                          : wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
 }
 
@@ -783,9 +842,10 @@ uint64_t m4rw_steps(uint64_t n, const Plan &p)
     return (n + GB - 1) / GB;
 }
 
-uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p)
+uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p, bool half)
 {
-    return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * 4 + 255) & ~255ull;
+    // 32-bit entries, or 16 bits for the paired tables' staged leaves
+    return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * (half && plan_pairs(p) ? 2 : 4) + 255) & ~255ull;
 }
 
 bool leaf_staging_supported(const ReadGeom &g, const Plan &p, uint32_t leaves)
@@ -806,8 +866,19 @@ hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t 
     const uint32_t chunks = (uint32_t)((pairs + 1 + PAIR_CHUNK - 1) / PAIR_CHUNK);
     const uint32_t Bp = padded_rows(g.B);
     const uint32_t G = plan_pair_g(p);
+    LeafCombos lc{};
+    for (uint32_t l = 0; l < t.leaves; ++l) {
+        if (t.a_cnt[l] > 4)
+            return hipErrorInvalidValue;
+        lc.w[l] = t.a_cnt[l];
+        for (uint32_t e = 0; e < t.a_cnt[l]; ++e) {
+            if ((t.a[l][e] >> 4) >= t.grid || (t.a[l][e] & 15u) >= t.grid)
+                return hipErrorInvalidValue;
+            lc.w[l] |= (uint32_t)(((t.a[l][e] >> 4) << 4 | (t.a[l][e] & 15u)) & 63u) << (4 + 6 * e);
+        }
+    }
     auto k = G == 5 ? stage_leaf_pairs_kernel<5> : G == 4 ? stage_leaf_pairs_kernel<4> : stage_leaf_pairs_kernel<3>;
-    hipLaunchKernelGGL(k, dim3(Bp / 64, t.leaves, chunks), dim3(256), 0, stream, t, static_cast<const uint32_t *>(Q),
+    hipLaunchKernelGGL(k, dim3(Bp / 64, t.leaves, chunks), dim3(256), 0, stream, lc, static_cast<const uint32_t *>(Q),
                        qpitch / 4, B, n, g.B, g.n / 32, static_cast<uint32_t *>(staged), leaf_bytes / 4, Bp, pairs);
     return hipGetLastError();
 }
@@ -823,7 +894,8 @@ uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
 hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hipStream_t stream, hipEvent_t eb,
                      hipEvent_t ee)
 {
-    WideFn fn = plan_fn(p);
+    const bool staged = g.staged && plan_pairs(p);  // 16-bit entries staged for leaves
+    WideFn fn = plan_fn(p, staged);
     if (!fn)
         return hipErrorInvalidValue;
     WideArgs a{};
@@ -835,7 +907,7 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.Bp = padded_rows(g.B);
     a.groups = m4rw_steps(g.n, p);
     uint32_t *qs = static_cast<uint32_t *>(partials);
-    if (g.staged && plan_pairs(p)) {
+    if (staged) {
         qs = const_cast<uint32_t *>(g.staged);
     } else {
         if (plan_pairs(p)) {
@@ -860,8 +932,8 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
             return e;
     }
     a.Qs = qs;
-    if (!(g.staged && plan_pairs(p)))
-        partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g, p);
+    if (!staged)
+        partials = static_cast<uint8_t *>(partials) + m4rw_staging_bytes(g, p, false);
     const uint32_t R = p.tile * p.unroll;
     a.n_rt = (g.B + R - 1) / R;
     a.splits = p.splits;
