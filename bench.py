@@ -43,21 +43,28 @@ LDS_READ_BPC, LDS_WRITE_BPC = 204.9, 75.4
 
 def lds_floor(plan, n: int, B: int, bucket_bytes: int):
     """Algorithmic LDS traffic of a Four-Russians (wide) read launch and the
-    time it takes at the measured LDS rates: every request looks up one 1 KiB
-    table row per table (a 6-bucket table, or two 5-bucket tables per step
-    with paired tables), and every workgroup writes its step's tables once."""
+    time it takes at the measured LDS rates: every request looks up one table
+    row slice per table (a 6-bucket table, or two G-bucket tables per step
+    with paired tables: G = 5, 4 or 3, or 6 with half waves), and every
+    workgroup writes its step's tables once. Slices are 1 KiB (64 lanes x 16
+    bytes), or 512 bytes with half waves (a request per 32 lanes)."""
     if plan.kind != 4:
         return None
     pairs = bool(plan.flags & (1 << 13))
-    per_step = 10 if pairs else 6
-    tables, entries = (2, 32) if pairs else (1, 64)
+    half = pairs and bool(plan.flags & (1 << 16))
+    if pairs:
+        G = 6 if plan.flags & (1 << 17) else 5 - ((plan.flags >> 14) & 3)
+        per_step, tables, entries = 2 * G, 2, 1 << G
+    else:
+        per_step, tables, entries = 6, 1, 64
+    entry = 512 if half else 1024
     steps = -(-n // per_step)
-    slices = -(-bucket_bytes // 1024)
+    slices = -(-bucket_bytes // entry)
     R = plan.tile * plan.unroll
     tiles = -(-B // R)
     rows = -(-B // plan.tile) * plan.tile              # requests of the active waves
-    rd = slices * steps * rows * tables * 1024
-    wr = slices * tiles * steps * tables * entries * 1024
+    rd = slices * steps * rows * tables * entry
+    wr = slices * tiles * steps * tables * entries * entry
     clk = 256 * 2.4e9
     floor_s = rd / (LDS_READ_BPC * clk) + wr / (LDS_WRITE_BPC * clk)
     return {"read_bytes": rd, "write_bytes": wr, "floor_ms": round(1e3 * floor_s, 4)}
@@ -118,12 +125,13 @@ def measured_traffic(workload: str, plan) -> float | None:
 KERNEL_NAMES = {1: "xorpir_tile_kernel", 2: "xorpir_tile_kernel", 3: "xorpir_m4r_kernel",
                 4: "xorpir_m4rw_kernel"}
 PLAN_PAIRS = 1 << 13
+PLAN_HALF_WAVES = 1 << 16
 
 
 def kernel_name(plan: dict) -> str:
     """Name of the main read kernel a plan launches."""
     if plan["kind"] == 4 and plan["flags"] & PLAN_PAIRS:
-        return "xorpir_m4rp_kernel"
+        return "xorpir_m4rh_kernel" if plan["flags"] & PLAN_HALF_WAVES else "xorpir_m4rp_kernel"
     return KERNEL_NAMES[plan["kind"]]
 
 
@@ -793,8 +801,8 @@ def fixed_bench(args, pir, torch, w, B: int, K: int, W: int, cpu_rows: int, cpu_
         unit = 32 << args.prep
         nq, bq, cq = -(-w.n // unit) * unit >> args.prep, -(-B // (1 << args.prep)), w.bucket_bytes >> args.prep
         # the leaves take the automatic plan of their shape: the same family as
-        # this batch's while both are above 128 requests
-        one = lds_floor(plan, nq, bq, cq) if bq > 128 and B > 128 else None
+        # this batch's while both are above 256 requests
+        one = lds_floor(plan, nq, bq, cq) if bq > 256 and B > 256 else None
         lds = None if one is None else {"read_bytes": one["read_bytes"] * leaves,
                                         "write_bytes": one["write_bytes"] * leaves,
                                         "floor_ms": round(one["floor_ms"] * leaves, 4), "leaves": leaves}

@@ -233,13 +233,19 @@ enum pir_kernel_kind {
  * each request folding both lookups in with one 3-input XOR per dword
  * (rolling lookups always). PAIR_G4 / PAIR_G3 (with PAIRS): paired tables of
  * 4 or 3 buckets (16 or 8 entries, 64 or 32 KiB of LDS double-buffered, two
- * workgroups per CU) for batches of tens of requests. */
+ * workgroups per CU) for batches of tens of requests. HALF_WAVES (with
+ * PAIRS, 5-bucket tables or PAIR_G6's 6-bucket ones): 512-byte table
+ * entries, each 32-lane half of a wave serving its own request, so a
+ * workgroup answers twice the requests from one set of tables (tile =
+ * requests per wave, 64 or 32). */
 enum {
     PIR_PLAN_SHARED_COLUMN = 1,
     PIR_PLAN_ROLLING = 1 << 12,
     PIR_PLAN_PAIRS = 1 << 13,
     PIR_PLAN_PAIR_G4 = 1 << 14,
-    PIR_PLAN_PAIR_G3 = 2 << 14
+    PIR_PLAN_PAIR_G3 = 2 << 14,
+    PIR_PLAN_HALF_WAVES = 1 << 16,
+    PIR_PLAN_PAIR_G6 = 1 << 17
 };
 
 /* A read schedule: kernel family, request tile (requests per wave), bucket
@@ -255,7 +261,9 @@ typedef struct pir_plan {
 
 /* Force a schedule for subsequent reads of this handle (kind AUTO restores
  * the automatic choice: MASK up to 16 requests, paired 4-bucket tables up to
- * 128, paired 5-bucket tables above, unless the tuning table has an entry).
+ * 128, paired 5-bucket tables up to 256, half-wave paired 6-bucket tables
+ * above over rows of 512 bytes or more, unless the tuning table has an
+ * entry).
  * PIR_EINVAL for an unsupported combination. */
 int pir_set_plan(pir_db *db, const pir_plan *plan);
 

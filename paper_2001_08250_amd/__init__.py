@@ -29,6 +29,8 @@ PLAN_ROLLING = 1 << 12
 PLAN_PAIRS = 1 << 13
 PLAN_PAIR_G4 = 1 << 14     # with PLAN_PAIRS: 4-bucket tables
 PLAN_PAIR_G3 = 2 << 14     # with PLAN_PAIRS: 3-bucket tables
+PLAN_HALF_WAVES = 1 << 16  # with PLAN_PAIRS: 512-byte entries, a request per half wave
+PLAN_PAIR_G6 = 1 << 17     # with PLAN_PAIRS | PLAN_HALF_WAVES: 6-bucket tables
 PROFILE_MAX = 4096
 IV_DEFAULT_BITS, IV_DEFAULT_WINDOW = 1 << 17, 100   # the library's interest-vector defaults
 

@@ -60,6 +60,10 @@ constexpr uint32_t PLAN_ROLLING = 1u << 12;
 // paired tables of 5 - ((flags >> PLAN_PAIR_G_SHIFT) & 3) buckets each (5, 4 or 3)
 constexpr uint32_t PLAN_PAIR_G_SHIFT = 14;
 constexpr uint32_t PLAN_PAIRS = 1u << 13;
+// with PLAN_PAIRS: 512-byte table entries, one request per 32-lane half wave
+// (xorpir_m4rh_kernel); with PLAN_PAIR_G6 too, 6-bucket tables
+constexpr uint32_t PLAN_HALF_WAVES = 1u << 16;
+constexpr uint32_t PLAN_PAIR_G6 = 1u << 17;
 
 // Device scratch the read needs for split partials: bytes.
 uint64_t partial_bytes(const ReadGeom &g, const Plan &p);

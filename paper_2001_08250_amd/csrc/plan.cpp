@@ -65,8 +65,17 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         // up to 256 requests per CU) above, where their fewer lookups per
         // request outweigh the larger table builds. A request tile covers
         // the whole batch up to 256 requests (a second tile would build
-        // every table again).
-        if (g.B > 128) {
+        // every table again). Above 256 requests over rows of 512 bytes or
+        // more, 6-bucket tables of 512-byte entries, a request per half
+        // wave, 512 requests a workgroup: 12 buckets per two lookups (73.0
+        // against 80.8 ms for 2048 requests over 2^22 rows of 4 KiB; 1.18
+        // against 1.32 ms for 512 over 2^20 of 1 KiB).
+        if (g.B > 256 && g.stride >= 512) {
+            p.kind = KIND_M4RW;
+            p.flags = PLAN_PAIRS | PLAN_HALF_WAVES | PLAN_PAIR_G6;
+            p.unroll = 8;
+            p.tile = 64;
+        } else if (g.B > 128) {
             p.kind = KIND_M4RW;
             p.flags = PLAN_PAIRS;
             p.unroll = 8;
@@ -101,10 +110,10 @@ Plan resolve_plan(const ReadGeom &g, Plan want, int num_cus)
         per_cu = 2;  // one 128 KiB LDS table pair per CU at a time
     } else if (p.kind == KIND_M4RW) {
         if (p.tile == 0)
-            p.tile = g.B > 128 ? 32 : 16;
+            p.tile = (p.flags & PLAN_HALF_WAVES) ? 64 : g.B > 128 ? 32 : 16;
         if (p.unroll == 0)
             p.unroll = 8;
-        units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, 0});
+        units = m4rw_tasks(g, Plan{p.kind, p.tile, 1, p.unroll, p.flags});
         // double-buffered tables of 128 KiB fill a CU's LDS; paired 4- and
         // 3-bucket tables (64 / 32 KiB) let two workgroups share it
         per_cu = ((p.flags & PLAN_PAIRS) && ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u)) ? 2 : 1;

@@ -116,6 +116,22 @@ int pir_tune(pir_db *db, uint32_t B, uint32_t iters, pir_plan *best, double *bes
             }
         }
     }
+    for (uint32_t fl : {PLAN_PAIRS | PLAN_HALF_WAVES | PLAN_PAIR_G6, PLAN_PAIRS | PLAN_HALF_WAVES}) {
+        for (uint32_t t : {32u, 64u}) {
+            if (t * 8 > 2 * std::max<uint32_t>(B, 32) || g.stride < 512)
+                continue;
+            Plan base = resolve_plan(g, Plan{KIND_M4RW, t, 0, 8, fl}, db->num_cus);
+            for (uint32_t sm : {1u, 2u}) {
+                Plan a = base, b = base;
+                a.splits = std::max<uint32_t>(1, base.splits / sm);
+                b.splits = base.splits * sm;
+                if (plan_supported(a))
+                    cands.push_back(a);
+                if (sm > 1 && plan_supported(b))
+                    cands.push_back(b);
+            }
+        }
+    }
     for (uint32_t nw : {4u, 8u, 16u})
     for (uint32_t fl : {2u << 8, 3u << 8, 4u << 8, PLAN_ROLLING, PLAN_ROLLING | (3u << 8), PLAN_PAIRS,
                         PLAN_PAIRS | (3u << 8), PLAN_PAIRS | (1u << PLAN_PAIR_G_SHIFT),

@@ -562,6 +562,202 @@ void xorpir_m4rp_kernel(const WideArgs a)
     }
 }
 
+// Half-wave pair tables (PLAN_HALF_WAVES): the paired tables above with
+// 512-byte entries, one per 32-lane half of a wave. Each half serves its own
+// request over a 512-byte column slice, so a lane holds TW / 2 accumulators
+// for a wave of TW requests and a workgroup of NW waves answers NW * TW
+// requests (512 at 8 x 64) from one set of tables: against the 1 KiB-entry
+// form at the same registers, a table entry serves twice the requests, which
+// halves the tables' LDS writes per answer byte, while the lookups move the
+// same bytes. Both halves load the same D rows (one address per pair of
+// lanes); each build instruction writes two entries, one per half. The
+// request bits are staged as 16-bit entries (word i of a wave's pair row
+// holds its requests 2i and 2i + 1), and a lane takes its request's G-bit
+// index with one vector bit-field extract at its half's shift (0 or 16) and
+// forms the entry address with one shift-or. G = 5: 32 KiB per set, 64 KiB
+// double-buffered; G = 6: 64 / 128 KiB.
+template <int G>
+struct HalfShape {
+    static constexpr int E = 1 << G;                 // entries per table
+    static constexpr int ENTRY = 512;                // bytes per entry
+    static constexpr int TABLE_U4 = E * ENTRY / 16;
+    static constexpr int SET_U4 = 2 * TABLE_U4;
+    static constexpr int SET_BYTES = SET_U4 * 16;
+};
+
+// Wave wt of the WPT waves that build one table: half hw of the wave writes
+// entries (wt << LB) | (hw << (LB - 1)) | x, x < 2^(LB - 1), in Gray code
+// order (d holds this lane's 16 bytes of the table's G rows).
+template <int WPT, int G>
+__device__ __forceinline__ void build_hw(uint4 *__restrict__ tbl, const uint4 (&d)[G], uint32_t wt, uint32_t lane)
+{
+    constexpr int LW = log2_waves<WPT>();
+    constexpr int LB = G - LW;
+    static_assert(LB >= 1, "each half-wave builds at least one entry");
+    const uint32_t hw = lane >> 5;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int b = 0; b < LW; ++b)
+        if ((wt >> b) & 1u)
+            xor4(v, d[LB + b]);
+    const uint32_t m = 0u - hw;  // all ones in the upper half
+    v.x ^= d[LB - 1].x & m;
+    v.y ^= d[LB - 1].y & m;
+    v.z ^= d[LB - 1].z & m;
+    v.w ^= d[LB - 1].w & m;
+    uint4 *w = tbl + (((wt << LB) | (hw << (LB - 1))) * 32u + (lane & 31u));
+    w[0] = v;
+#pragma unroll
+    for (int k = 1; k < (1 << (LB - 1)); ++k) {
+        xor4(v, d[__builtin_ctz(k)]);
+        w[(k ^ (k >> 1)) * 32] = v;
+    }
+}
+
+// Lookups of a wave's TW requests, two per instruction: the lane's half hs
+// (0 or 16) picks its request's 16-bit entry out of off[i].
+template <int G, int TWH, int INFL>
+__device__ __forceinline__ void lookup_hw(uint4 (&acc)[TWH], const uint8_t *lds_bytes, uint32_t lane_base,
+                                          uint32_t hs, const uint32_t (&off)[TWH])
+{
+    constexpr uint32_t TB = (uint32_t)HalfShape<G>::TABLE_U4 * 16;  // table B follows table A in the set
+    const uint32_t hsb = hs + G;
+    uint4 ta[INFL], tb[INFL];
+#pragma unroll
+    for (int i = 0; i < INFL; ++i) {
+        ta[i] = *reinterpret_cast<const uint4 *>(lds_bytes + ((__builtin_amdgcn_ubfe(off[i], hs, G) << 9) | lane_base));
+        tb[i] = *reinterpret_cast<const uint4 *>(lds_bytes + TB +
+                                                 ((__builtin_amdgcn_ubfe(off[i], hsb, G) << 9) | lane_base));
+    }
+#pragma unroll
+    for (int r = 0; r < TWH; ++r) {
+        __builtin_amdgcn_sched_barrier(0);
+        xor3x4(acc[r], ta[r % INFL], tb[r % INFL]);
+        if (r + INFL < TWH) {
+            const uint32_t w = off[r + INFL];
+            ta[r % INFL] = *reinterpret_cast<const uint4 *>(lds_bytes + ((__builtin_amdgcn_ubfe(w, hs, G) << 9) | lane_base));
+            tb[r % INFL] = *reinterpret_cast<const uint4 *>(lds_bytes + TB +
+                                                            ((__builtin_amdgcn_ubfe(w, hsb, G) << 9) | lane_base));
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One pair step of the half-wave kernel (the order of pair_step).
+template <int NW, int TWH, int P, int K, int G>
+__device__ __forceinline__ void hw_step(uint4 (&acc)[TWH], uint4 (&ring)[P][G], uint32_t (&offs)[TWH], uint4 *lds,
+                                        const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
+                                        uint64_t y, const uint32_t *__restrict__ Qw, uint32_t Bw, bool active,
+                                        uint32_t half, uint32_t wt, uint32_t lane, uint32_t hs)
+{
+    using S = HalfShape<G>;
+    constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
+    load_half<G>(ring[slot], D, row_bytes, lane_off, y + P, half);
+    if (active) {
+        lookup_hw<G, TWH, 4>(acc, reinterpret_cast<const uint8_t *>(lds),
+                             (uint32_t)(buf * S::SET_BYTES) | ((lane & 31u) * 16u), hs, offs);
+        // the next pair's staged words (rows r0 .. r0 + 2 TWH - 1 < Bp of
+        // pair y + 1 <= pairs, Bw words a pair); the index goes through
+        // readfirstlane for the reason given in group_step
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(y + 1));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((y + 1) >> 32));
+        const uint32_t *qn = Qw + (((uint64_t)hi << 32) | lo) * Bw;
+#pragma unroll
+        for (int i = 0; i < TWH; ++i)
+            offs[i] = qn[i];
+    }
+    build_hw<NW / 2, G>(lds + (buf ^ 1) * S::SET_U4 + half * S::TABLE_U4, ring[next], wt, lane);
+    __syncthreads();
+}
+
+template <int NW, int TWH, int P, int K, int U, int G>
+__device__ __forceinline__ void hw_steps(uint4 (&acc)[TWH], uint4 (&ring)[P][G], uint32_t (&offs)[TWH], uint4 *lds,
+                                         const uint8_t *__restrict__ D, uint64_t row_bytes, uint32_t lane_off,
+                                         uint64_t y, uint64_t left, const uint32_t *__restrict__ Qw, uint32_t Bw,
+                                         bool active, uint32_t half, uint32_t wt, uint32_t lane, uint32_t hs)
+{
+    if constexpr (K < U) {
+        if ((uint64_t)K < left) {
+            hw_step<NW, TWH, P, K, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y + K, Qw, Bw, active, half, wt,
+                                      lane, hs);
+            hw_steps<NW, TWH, P, K + 1, U, G>(acc, ring, offs, lds, D, row_bytes, lane_off, y, left, Qw, Bw, active,
+                                              half, wt, lane, hs);
+        }
+    }
+}
+
+// Task layout and outputs of xorpir_m4rp_kernel with 512-byte column slices
+// (a.slices counts them) and NW * TW requests per workgroup.
+template <int NW, int TW, int P, int G>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+void xorpir_m4rh_kernel(const WideArgs a)
+{
+    static_assert(NW >= 4 && NW <= 16 && TW % 2 == 0, "two tables built by NW / 2 waves each; two requests a word");
+    constexpr int TWH = TW / 2;
+    using S = HalfShape<G>;
+    constexpr int U = (P % 2 == 0) ? P : 2 * P;
+    __shared__ uint4 lds[2 * S::SET_U4];
+    const uint32_t L = blockIdx.x;
+    const uint32_t t = (L & 7u) * a.tasks_per_xcd + (L >> 3);
+    if (t >= a.tasks)
+        return;
+    const uint32_t rt = t % a.n_rt;
+    const uint32_t rest = t / a.n_rt;
+    const uint32_t slice = rest % a.slices;
+    const uint32_t rest2 = rest / a.slices;
+    const uint32_t s = rest2 % a.splits;
+    const uint32_t leaf = rest2 / a.splits;
+    const uint8_t *D = a.D + leaf * a.leaf_d_bytes;
+
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t half = wave / (NW / 2), wt = wave % (NW / 2);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t hw = lane >> 5, hs = hw * 16u;
+    const uint32_t col = slice * 32u + (lane & 31u);
+    const bool col_ok = col < a.stride16;
+    const uint32_t lane_off = (col_ok ? col : slice * 32u) * 16u;
+    const uint32_t r0 = rt * (NW * TW) + wave * TW;
+    const bool active = r0 < a.B;
+
+    const uint64_t gb = (uint64_t)s * a.groups_per_split;
+    const uint64_t ge = std::min<uint64_t>(a.groups, gb + a.groups_per_split);
+
+    uint4 acc[TWH];
+#pragma unroll
+    for (int r = 0; r < TWH; ++r)
+        acc[r] = make_uint4(0u, 0u, 0u, 0u);
+
+    if (gb < ge) {
+        uint4 ring[P][G];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            load_half<G>(ring[k], D, a.row_bytes, lane_off, gb + k, half);
+        const uint32_t Bw = a.Bp / 2;
+        const uint32_t *Qw = a.Qs + leaf * a.leaf_qs + r0 / 2;
+        uint32_t offs[TWH] = {};
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < TWH; ++i)
+                offs[i] = Qw[gb * Bw + i];
+        }
+        build_hw<NW / 2, G>(lds + half * S::TABLE_U4, ring[0], wt, lane);
+        __syncthreads();
+        for (uint64_t y = gb; y < ge; y += U)
+            hw_steps<NW, TWH, P, 0, U, G>(acc, ring, offs, lds, D, a.row_bytes, lane_off, y, ge - y, Qw, Bw, active,
+                                          half, wt, lane, hs);
+    }
+
+    if (active && col_ok) {
+        uint4 *o = reinterpret_cast<uint4 *>(a.out) + leaf * a.leaf_out16 + (uint64_t)s * a.out_split16 + col;
+#pragma unroll
+        for (int i = 0; i < TWH; ++i) {
+            const uint32_t r = r0 + 2 * i + hw;
+            if (r < a.B)
+                o[(uint64_t)r * a.out_row16] = acc[i];
+        }
+    }
+}
+
 // Qs[y * Bp + r] for pair y and request row r, with a / b the G request bits
 // of tables A / B (bits >= n cleared): as 32-bit entries (B << 16) | A, A =
 // a * 1024 and B = b * 1024 + 2^G KiB (table B's offset within the set;
@@ -604,7 +800,7 @@ __device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_
     }
 }
 
-template <int G>
+template <int G, bool H>
 __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t *__restrict__ Q, uint64_t qpitch_w,
                                                                  uint32_t B, uint64_t n, uint32_t *__restrict__ Qs,
                                                                  uint32_t Bp, uint64_t pairs)
@@ -636,7 +832,7 @@ __global__ __launch_bounds__(256) void stage_pair_offsets_kernel(const uint32_t 
     if (t < 64)
         bits[t * RS + W] = 0u;  // the high word of the chunk's last window
     __syncthreads();
-    write_pair_offsets<G, false>(bits, (uint64_t)blockIdx.x * PAIR_CHUNK, pairs, Qs, Bp, r0);
+    write_pair_offsets<G, H>(bits, (uint64_t)blockIdx.x * PAIR_CHUNK, pairs, Qs, Bp, r0);
 }
 
 // Pair entries (16-bit) of every leaf of a preprocessed read, staged
@@ -813,13 +1009,40 @@ WideFn pair_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g, bool half)
     return half ? pair_fn_h<true>(nw, tw, depth, g) : pair_fn_h<false>(nw, tw, depth, g);
 }
 
+// Half-wave kernels: tw = requests per wave (two per lane pair).
+WideFn hw_fn(uint32_t nw, uint32_t tw, uint32_t depth, uint32_t g)
+{
+    if (depth == 0)
+        depth = 2;
+    if (g == 5) {
+        if (nw == 8 && tw == 64 && depth == 2) return xorpir_m4rh_kernel<8, 64, 2, 5>;
+        if (nw == 8 && tw == 64 && depth == 3) return xorpir_m4rh_kernel<8, 64, 3, 5>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rh_kernel<8, 32, 2, 5>;
+        if (nw == 4 && tw == 64 && depth == 2) return xorpir_m4rh_kernel<4, 64, 2, 5>;
+    } else if (g == 6) {
+        if (nw == 8 && tw == 64 && depth == 2) return xorpir_m4rh_kernel<8, 64, 2, 6>;
+        if (nw == 8 && tw == 32 && depth == 2) return xorpir_m4rh_kernel<8, 32, 2, 6>;
+    }
+    return nullptr;
+}
+
 uint32_t plan_depth(const Plan &p) { return (p.flags >> 8) & 15u; }
-uint32_t plan_pair_g(const Plan &p) { return 5u - ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u); }
+uint32_t plan_pair_g(const Plan &p)
+{
+    return (p.flags & PLAN_PAIR_G6) ? 6u : 5u - ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u);
+}
+bool plan_half_waves(const Plan &p) { return (p.flags & PLAN_PAIRS) && (p.flags & PLAN_HALF_WAVES); }
 uint32_t plan_mode(const Plan &p) { return (p.flags & PLAN_ROLLING) ? 1u : 0u; }
 bool plan_pairs(const Plan &p) { return (p.flags & PLAN_PAIRS) != 0; }
 
 WideFn plan_fn(const Plan &p, bool half = false)
 {
+    // G6 only with half waves; half waves only with paired 5- or 6-bucket tables
+    if (((p.flags & PLAN_PAIR_G6) || (p.flags & PLAN_HALF_WAVES)) && !plan_half_waves(p))
+        return nullptr;
+    if (plan_half_waves(p))
+        return ((p.flags >> PLAN_PAIR_G_SHIFT) & 3u) ? nullptr
+                                                      : hw_fn(p.unroll, p.tile, plan_depth(p), plan_pair_g(p));
     return plan_pairs(p) ? pair_fn(p.unroll, p.tile, plan_depth(p), plan_pair_g(p), half)
                          : wide_fn(p.unroll, p.tile, plan_depth(p), plan_mode(p));
 }
@@ -844,8 +1067,10 @@ uint64_t m4rw_steps(uint64_t n, const Plan &p)
 
 uint64_t m4rw_staging_bytes(const ReadGeom &g, const Plan &p, bool half)
 {
-    // 32-bit entries, or 16 bits for the paired tables' staged leaves
-    return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * (half && plan_pairs(p) ? 2 : 4) + 255) & ~255ull;
+    // 32-bit entries, or 16 bits for the half-wave kernels and the paired
+    // tables' staged leaves
+    const bool h16 = plan_half_waves(p) || (half && plan_pairs(p));
+    return ((m4rw_steps(g.n, p) + 1) * padded_rows(g.B) * (h16 ? 2 : 4) + 255) & ~255ull;
 }
 
 bool leaf_staging_supported(const ReadGeom &g, const Plan &p, uint32_t leaves)
@@ -877,7 +1102,10 @@ hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t 
             lc.w[l] |= (uint32_t)(((t.a[l][e] >> 4) << 4 | (t.a[l][e] & 15u)) & 63u) << (4 + 6 * e);
         }
     }
-    auto k = G == 5 ? stage_leaf_pairs_kernel<5> : G == 4 ? stage_leaf_pairs_kernel<4> : stage_leaf_pairs_kernel<3>;
+    auto k = G == 6   ? stage_leaf_pairs_kernel<6>
+             : G == 5 ? stage_leaf_pairs_kernel<5>
+             : G == 4 ? stage_leaf_pairs_kernel<4>
+                      : stage_leaf_pairs_kernel<3>;
     hipLaunchKernelGGL(k, dim3(Bp / 64, t.leaves, chunks), dim3(256), 0, stream, lc, static_cast<const uint32_t *>(Q),
                        qpitch / 4, B, n, g.B, g.n / 32, static_cast<uint32_t *>(staged), leaf_bytes / 4, Bp, pairs);
     return hipGetLastError();
@@ -886,7 +1114,8 @@ hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t 
 uint32_t m4rw_tasks(const ReadGeom &g, const Plan &p)
 {
     const uint32_t stride16 = (uint32_t)(g.stride / 16);
-    const uint32_t slices = (stride16 + 63) / 64;
+    const uint32_t sw = plan_half_waves(p) ? 32 : 64;  // 16-byte columns per slice
+    const uint32_t slices = (stride16 + sw - 1) / sw;
     const uint32_t R = std::max<uint32_t>(1, p.tile * p.unroll);
     return ((g.B + R - 1) / R) * slices;
 }
@@ -895,6 +1124,7 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
                      hipEvent_t ee)
 {
     const bool staged = g.staged && plan_pairs(p);  // 16-bit entries staged for leaves
+    const bool hwp = plan_half_waves(p);              // 16-bit entries, 512-byte slices
     WideFn fn = plan_fn(p, staged);
     if (!fn)
         return hipErrorInvalidValue;
@@ -902,7 +1132,7 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
     a.D = static_cast<const uint8_t *>(g.D);
     a.row_bytes = g.stride;
     a.stride16 = (uint32_t)(g.stride / 16);
-    a.slices = (a.stride16 + 63) / 64;
+    a.slices = hwp ? (a.stride16 + 31) / 32 : (a.stride16 + 63) / 64;
     a.B = g.B;
     a.Bp = padded_rows(g.B);
     a.groups = m4rw_steps(g.n, p);
@@ -915,8 +1145,10 @@ hipError_t launch_m4rw_read(const ReadGeom &g, const Plan &p, void *partials, hi
             if (chunks * 256 > 0xffffffffull)  // a grid dimension holds fewer than 2^32 work-items
                 return hipErrorInvalidValue;
             const uint32_t G = plan_pair_g(p);
-            auto stage = G == 5 ? stage_pair_offsets_kernel<5>
-                                : G == 4 ? stage_pair_offsets_kernel<4> : stage_pair_offsets_kernel<3>;
+            auto stage = hwp ? (G == 6 ? stage_pair_offsets_kernel<6, true> : stage_pair_offsets_kernel<5, true>)
+                         : G == 5 ? stage_pair_offsets_kernel<5, false>
+                         : G == 4 ? stage_pair_offsets_kernel<4, false>
+                                  : stage_pair_offsets_kernel<3, false>;
             hipLaunchKernelGGL(stage, dim3((uint32_t)chunks, a.Bp / 64), dim3(256), 0, stream,
                                static_cast<const uint32_t *>(g.Q), g.qpitch / 4, g.B, g.n, qs, a.Bp, a.groups);
         } else {

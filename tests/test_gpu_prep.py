@@ -46,6 +46,8 @@ _P = pir.PLAN_PAIRS
 LEAF_PLANS = [(pir.KERNEL_M4R_WIDE, 32, 0, 8, _P), (pir.KERNEL_M4R_WIDE, 32, 3, 4, _P),
               (pir.KERNEL_M4R_WIDE, 16, 0, 8, _P | 4 << 8), (pir.KERNEL_M4R_WIDE, 8, 5, 8, _P | pir.PLAN_PAIR_G4),
               (pir.KERNEL_M4R_WIDE, 4, 0, 8, _P | pir.PLAN_PAIR_G3), (pir.KERNEL_M4R_WIDE, 8, 1, 8, _P | 4 << 8),
+              (pir.KERNEL_M4R_WIDE, 64, 0, 8, _P | pir.PLAN_HALF_WAVES),
+              (pir.KERNEL_M4R_WIDE, 32, 3, 8, _P | pir.PLAN_HALF_WAVES | pir.PLAN_PAIR_G6),
               (pir.KERNEL_M4R_WIDE, 16, 0, 8, pir.PLAN_ROLLING),
               (pir.KERNEL_MASK, 4, 0, 8, 0)]
 

@@ -59,12 +59,15 @@ _R, _P = pir.PLAN_ROLLING, pir.PLAN_PAIRS
 # (waves, requests per wave, flags = prefetch depth << 8 | lookup mode)
 _G4 = pir.PLAN_PAIRS | pir.PLAN_PAIR_G4   # paired 4-bucket tables
 _G3 = pir.PLAN_PAIRS | pir.PLAN_PAIR_G3   # paired 3-bucket tables
+_HW = pir.PLAN_PAIRS | pir.PLAN_HALF_WAVES  # 512-byte entries, a request per half wave
+_G6 = pir.PLAN_PAIR_G6                     # with _HW: paired 6-bucket tables
 WIDE_SHAPES = [(4, 32, 2 << 8), (8, 16, 2 << 8), (8, 16, 4 << 8), (8, 32, 2 << 8), (8, 32, 3 << 8), (16, 16, 2 << 8),
                (4, 8, _R), (4, 16, _R), (8, 8, _R), (8, 16, _R), (8, 16, _R | 3 << 8), (8, 32, _R), (16, 16, _R),
                (4, 16, _P), (4, 32, _P), (8, 8, _P), (8, 16, _P), (8, 32, _P), (8, 32, _P | 3 << 8),
                (8, 4, _P | 4 << 8), (8, 8, _P | 4 << 8), (8, 16, _P | 4 << 8),
                (8, 4, _G4), (8, 4, _G4 | 4 << 8), (8, 8, _G4), (8, 8, _G4 | 4 << 8), (8, 16, _G4),
-               (8, 4, _G3), (8, 4, _G3 | 4 << 8), (8, 8, _G3), (8, 8, _G3 | 4 << 8)]
+               (8, 4, _G3), (8, 4, _G3 | 4 << 8), (8, 8, _G3), (8, 8, _G3 | 4 << 8),
+               (8, 64, _HW), (8, 64, _HW | 3 << 8), (8, 32, _HW), (4, 64, _HW), (8, 64, _HW | _G6), (8, 32, _HW | _G6)]
 FOUR_RUSSIANS = ([(pir.KERNEL_M4R, (nw, tw, 0)) for nw, tw in M4R_SHAPES] +
                  [(pir.KERNEL_M4R_WIDE, s) for s in WIDE_SHAPES])
 
@@ -74,7 +77,7 @@ def test_four_russians_every_shape(kind):
     """Four-Russians kernels: every (waves, requests/wave) shape, splits, ragged B."""
     n, d, z = 1024, 4, 1024
     D = synth.uniform_db(1001, n, d * z)
-    reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300)}
+    reqs = {B: synth.bernoulli_requests(2200 + B, B, n) for B in (1, 37, 256, 300, 1100)}
     wants = {B: oracle.pir_read(D, r, threads=8) for B, r in reqs.items()}
     with _db(D, d, z) as db:
         for k, (nw, tw, fl) in FOUR_RUSSIANS:
@@ -256,6 +259,18 @@ def test_interest_window_across_commits(m_bits, window):
             epochs.append(pos)
             want = oracle.interest_window(m_bits, epochs, len(epochs) - 1, window)
             assert np.array_equal(db.interest_vector(), want), f"epoch {e}"
+
+
+def test_half_wave_plan_combinations_rejected():
+    """Half waves take 5- or 6-bucket paired tables only, and 6-bucket
+    tables only with half waves."""
+    with pir.PirDB(64, 1, 1024) as db:
+        for flags in (pir.PLAN_PAIR_G6 | pir.PLAN_PAIRS, pir.PLAN_HALF_WAVES | pir.PLAN_PAIRS | pir.PLAN_PAIR_G4,
+                      pir.PLAN_HALF_WAVES):
+            with pytest.raises(pir.PirError):
+                db.set_plan(pir.KERNEL_M4R_WIDE, 64, 0, 8, flags)
+        db.set_plan(pir.KERNEL_M4R_WIDE, 64, 0, 8, pir.PLAN_PAIRS | pir.PLAN_HALF_WAVES)
+        db.set_plan()
 
 
 def test_write_errors():
