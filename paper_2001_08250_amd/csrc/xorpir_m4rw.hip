@@ -654,7 +654,7 @@ __device__ __forceinline__ void hw_step(uint4 (&acc)[TWH], uint4 (&ring)[P][G], 
     constexpr int slot = K % P, next = (K + 1) % P, buf = K & 1;
     load_half<G>(ring[slot], D, row_bytes, lane_off, y + P, half);
     if (active) {
-        lookup_hw<G, TWH, 4>(acc, reinterpret_cast<const uint8_t *>(lds),
+        lookup_hw<G, TWH, 2>(acc, reinterpret_cast<const uint8_t *>(lds),
                              (uint32_t)(buf * S::SET_BYTES) | ((lane & 31u) * 16u), hs, offs);
         // the next pair's staged words (rows r0 .. r0 + 2 TWH - 1 < Bp of
         // pair y + 1 <= pairs, Bw words a pair); the index goes through
