@@ -778,6 +778,37 @@ __device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_
 {
     using S = PairShape<G>;
     constexpr int RS = PAIR_CHUNK * S::BUCKETS / 32 + 1;
+    if constexpr (H) {
+        // 16-bit entries: a thread packs 8 rows of one pair into one 16-byte
+        // store (r0 and Bp are multiples of 64, so every store is aligned)
+        static_assert(PAIR_CHUNK * 8 % 256 == 0, "whole tasks per thread");
+        for (uint32_t task = threadIdx.x; task < PAIR_CHUNK * 8; task += 256) {
+            const uint32_t k = task >> 3, g8 = (task & 7u) * 8u;
+            const uint64_t y = y0 + k;
+            if (y > pairs)
+                continue;
+            const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
+            uint32_t w[4];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const uint32_t *row = bits + (g8 + m) * RS;
+                const uint64_t win = (uint64_t)row[j] | ((uint64_t)row[j + 1] << 32);
+                const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
+                if (m & 1)
+                    w[m >> 1] |= v << 16;
+                else
+                    w[m >> 1] = v;
+            }
+            using u32x4 = __attribute__((ext_vector_type(4))) uint32_t;
+            u32x4 *dst = reinterpret_cast<u32x4 *>(reinterpret_cast<uint16_t *>(Qs) + y * Bp + r0 + g8);
+            const u32x4 val = {w[0], w[1], w[2], w[3]};
+            if constexpr (NT)
+                __builtin_nontemporal_store(val, dst);
+            else
+                *dst = val;
+        }
+        return;
+    }
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     for (uint32_t k = wave; k < PAIR_CHUNK; k += 4) {
         const uint64_t y = y0 + k;
@@ -786,17 +817,9 @@ __device__ __forceinline__ void write_pair_offsets(const uint32_t *bits, uint64_
         const uint32_t bit = k * S::BUCKETS, j = bit >> 5, sh = bit & 31u;
         const uint64_t win = (uint64_t)bits[lane * RS + j] | ((uint64_t)bits[lane * RS + j + 1] << 32);
         const uint32_t v = (uint32_t)(win >> sh) & ((1u << S::BUCKETS) - 1u);
-        if constexpr (H) {
-            uint16_t *Qh = reinterpret_cast<uint16_t *>(Qs) + y * Bp + r0 + lane;
-            if constexpr (NT)
-                __builtin_nontemporal_store((uint16_t)v, Qh);
-            else
-                *Qh = (uint16_t)v;
-        } else {
-            const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
-            const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
-            Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
-        }
+        const uint32_t ta = (v & (S::E - 1)) * ENTRY_BYTES;
+        const uint32_t tb = (v >> G) * ENTRY_BYTES + S::TABLE_U4 * 16;
+        Qs[y * Bp + r0 + lane] = (tb << 16) | ta;
     }
 }
 
@@ -851,7 +874,7 @@ struct LeafCombos {
     uint32_t w[PREP_MAX_LEAVES];
 };
 
-template <int G>
+template <int G, bool VEC>
 __global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const LeafCombos lc, const uint32_t *__restrict__ Q,
                                                                uint64_t qpitch_w, uint32_t B, uint64_t n, uint32_t Bq,
                                                                uint64_t Wq, uint32_t *__restrict__ Qs, uint64_t leaf_w,
@@ -867,38 +890,59 @@ __global__ __launch_bounds__(256) void stage_leaf_pairs_kernel(const LeafCombos 
     const uint64_t w0 = (uint64_t)blockIdx.z * W;
     const uint32_t lw = lc.w[leaf];
     const int cnt = lw & 15u;
-    // Every thread's words of every request block are loaded before any is
-    // used, so 4 x KW loads are in flight per thread: a word outside the
-    // rows, the bits or the leaf's count of blocks is loaded from word 0 of
-    // the requests (always present) and masked to zero.
-    constexpr int KW = (64 * W + 255) / 256;
     uint32_t blk[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         blk[e] = (lw >> (4 + 6 * e)) & 63u;
-    uint32_t got[4][KW];
+    // Every thread's words of every request block are loaded before any is
+    // used, so 4 x KW loads are in flight per thread: a word outside the
+    // rows, the bits or the leaf's count of blocks is loaded from word 0 of
+    // the requests (always present) and masked to zero. VEC: 16-byte loads
+    // (the row pitch, the leaf block width Wq and W are multiples of 4
+    // words, so a load never straddles a row or a block).
+    constexpr int WV = VEC ? 4 : 1;                 // words per load
+    constexpr int NL = 64 * W / WV;                 // loads per block and request block
+    constexpr int KW = (NL + 255) / 256;
+    static_assert(!VEC || W % 4 == 0, "16-byte loads cover whole chunks");
+    using u32x4 = __attribute__((ext_vector_type(4))) uint32_t;
+    u32x4 got[4][KW];
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
         const uint32_t i = t + 256u * k;
-        const uint32_t row = i / W, w = i % W;
+        const uint32_t row = i / (W / WV), w = (i % (W / WV)) * WV;
         const uint32_t lr = r0 + row;
         const uint64_t wi = w0 + w;
-        const bool in = i < 64u * W && lr < Bq && wi < Wq;
+        const bool in = i < (uint32_t)NL && lr < Bq && wi < Wq;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const uint64_t r = (uint64_t)(blk[e] >> 4) * Bq + lr;
             const uint64_t sw = (blk[e] & 15u) * Wq + wi;
             const uint64_t bit = sw * 32;
             const bool ok = in && e < cnt && r < B && bit < n;
-            const uint32_t keep = !ok ? 0u : bit + 32 > n ? (1u << (n - bit)) - 1u : ~0u;
-            got[e][k] = Q[ok ? r * qpitch_w + sw : 0] & keep;
+            const uint64_t at = ok ? r * qpitch_w + sw : 0;
+            if constexpr (VEC) {
+                u32x4 v = *reinterpret_cast<const u32x4 *>(Q + at);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint64_t b = bit + 32u * c;
+                    v[c] &= (!ok || b >= n) ? 0u : b + 32 > n ? (1u << (n - b)) - 1u : ~0u;
+                }
+                got[e][k] = v;
+            } else {
+                const uint32_t keep = !ok ? 0u : bit + 32 > n ? (1u << (n - bit)) - 1u : ~0u;
+                got[e][k][0] = Q[at] & keep;
+            }
         }
     }
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
         const uint32_t i = t + 256u * k;
-        if (i < 64u * W)
-            bits[(i / W) * RS + i % W] = got[0][k] ^ got[1][k] ^ got[2][k] ^ got[3][k];
+        if (i < (uint32_t)NL) {
+            const uint32_t row = i / (W / WV), w = (i % (W / WV)) * WV;
+#pragma unroll
+            for (int c = 0; c < WV; ++c)
+                bits[row * RS + w + c] = got[0][k][c] ^ got[1][k][c] ^ got[2][k][c] ^ got[3][k][c];
+        }
     }
     if (t < 64)
         bits[t * RS + W] = 0u;
@@ -1102,10 +1146,19 @@ hipError_t launch_stage_leaf_pairs(const PrepTables &t, const void *Q, uint64_t 
             lc.w[l] |= (uint32_t)(((t.a[l][e] >> 4) << 4 | (t.a[l][e] & 15u)) & 63u) << (4 + 6 * e);
         }
     }
-    auto k = G == 6   ? stage_leaf_pairs_kernel<6>
-             : G == 5 ? stage_leaf_pairs_kernel<5>
-             : G == 4 ? stage_leaf_pairs_kernel<4>
-                      : stage_leaf_pairs_kernel<3>;
+    // 16-byte loads when request rows and leaf blocks start on 16 bytes and
+    // a row's words (the bytes every row guarantees readable) are whole
+    // 16-byte units, so no load reaches past them
+    const bool vec = (qpitch % 16) == 0 && (g.n / 32) % 4 == 0 && ((n + 31) / 32) % 4 == 0 &&
+                     (reinterpret_cast<uintptr_t>(Q) & 15) == 0;
+    auto k = vec ? (G == 6   ? stage_leaf_pairs_kernel<6, true>
+                    : G == 5 ? stage_leaf_pairs_kernel<5, true>
+                    : G == 4 ? stage_leaf_pairs_kernel<4, true>
+                             : stage_leaf_pairs_kernel<3, true>)
+                 : (G == 6   ? stage_leaf_pairs_kernel<6, false>
+                    : G == 5 ? stage_leaf_pairs_kernel<5, false>
+                    : G == 4 ? stage_leaf_pairs_kernel<4, false>
+                             : stage_leaf_pairs_kernel<3, false>);
     hipLaunchKernelGGL(k, dim3(Bp / 64, t.leaves, chunks), dim3(256), 0, stream, lc, static_cast<const uint32_t *>(Q),
                        qpitch / 4, B, n, g.B, g.n / 32, static_cast<uint32_t *>(staged), leaf_bytes / 4, Bp, pairs);
     return hipGetLastError();

@@ -85,6 +85,32 @@ def test_leaf_reads_under_every_plan_family(levels):
 
 
 @pytest.mark.parametrize("levels", [1, 2])
+def test_leaf_staging_16_byte_request_loads(levels):
+    """Request rows of whole 16-byte units (n = 4070: 128 words, 6 bits of
+    the last one used) and leaf blocks of whole 16-byte units: the staging
+    loads 16 bytes at a time; host rows, device rows at a 16-byte pitch
+    wider than the row, and rows at an odd pitch (restaged) all bit-exact."""
+    import torch
+    n, d, z = 4070, 2, 512
+    D = synth.uniform_db(980 + levels, n, d * z)
+    with pir.PirDB(n, d, z) as db:
+        db.load(D)
+        db.preprocess(levels, min_batch=1)
+        for B in (97, 600):
+            req = synth.bernoulli_requests(990 + B, B, n)
+            want = oracle.pir_read(D, req, threads=8)
+            assert_rows_equal(db.read(req), want, f"L={levels} B={B} host rows")
+            qb = req.shape[1]
+            for pitch, off in ((528, 0), (qb + 5, 1)):
+                buf = torch.zeros((B, pitch + off), dtype=torch.uint8, device="cuda")
+                buf[:, off:off + qb] = torch.from_numpy(req).cuda()
+                out = torch.zeros((B, d * z), dtype=torch.uint8, device="cuda")
+                db.read_async(buf[:, off:off + qb], out)
+                torch.cuda.synchronize()
+                assert_rows_equal(out.cpu().numpy(), want, f"L={levels} B={B} pitch {pitch} offset {off}")
+
+
+@pytest.mark.parametrize("levels", [1, 2])
 def test_preprocessed_reads_follow_epochs_and_masks(levels):
     """Commits that change the snapshot rebuild the leaves: reads after each
     commit see its data; masked reads give the masked answers; one-hot
