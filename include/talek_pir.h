@@ -486,9 +486,10 @@ int pir_serve_run(pir_db *db, pir_cuckoo *table, const pir_serve_config *cfg,
  * large read does 7^L / 8^L of the plain product's work, at the price of
  * 7^L / 4^L times the snapshot in device memory (1.75 at L = 1, 3.06 at
  * L = 2), the commits' leaf upkeep, and per-read scratch of about
- * 7^L * (n / 2^L / 10 + 1) * ceil(B / 2^L) * 4 bytes of staged offsets plus
- * the leaves' split partials (10.5 GB and 3.2 GB for 2048 requests over
- * 2^22 buckets of 4 KiB at L = 2).
+ * 7^L * (n / 2^L / (2G) + 1) * ceil(B / 2^L) * 2 bytes of staged request
+ * entries (G = 6 buckets per table for leaves above 256 requests, else 5,
+ * 4 or 3) plus the leaves' split partials (4.4 GB and 3.2 GB for 2048
+ * requests over 2^22 buckets of 4 KiB at L = 2).
  *
  *   levels:    0 (off, frees the leaves), 1 or 2.
  *   min_batch: reads of B >= min_batch rows take the preprocessed path
