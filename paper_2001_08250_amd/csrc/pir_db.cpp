@@ -738,15 +738,15 @@ static LeafShape leaf_shape(const pir_db *db, uint32_t B)
     return l;
 }
 
-// Staged offsets of all leaves of one read above this many bytes go back to
+// Staged entries of all leaves of one read above this many bytes go back to
 // leaf request rows and a staging kernel per leaf; split partials of all
 // leaves above this many bytes, to a launch per leaf.
 constexpr uint64_t PREP_STAGE_MAX = 32ull << 30;
 constexpr uint64_t PREP_PARTIAL_MAX = 8ull << 30;
 
 // A preprocessed read's leaf geometry (D, Q and out set per leaf), plan,
-// what sc.leaf_q holds per leaf (the pair-table offsets of its request rows
-// when staged, else the rows themselves), the bytes per leaf answer block in
+// what sc.leaf_q holds per leaf (the 16-bit pair-table entries of its
+// request rows when staged, else the rows themselves), the bytes per leaf answer block in
 // sc.leaf_out, and whether one launch answers every leaf.
 struct LeafRead {
     LeafShape l;
@@ -759,7 +759,7 @@ struct LeafRead {
 // The request side of every leaf: it depends on the requests only, not on
 // the snapshot, so a read enqueues it before it waits for the latest
 // publication. Under a pair-table plan one launch stages every leaf's
-// table offsets straight from the request rows; otherwise the leaves'
+// table entries straight from the request rows; otherwise the leaves'
 // request rows are formed for their reads to stage.
 static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, uint32_t B, hipStream_t s,
                          LeafRead *lr)
@@ -800,7 +800,7 @@ static int prep_requests(pir_db *db, Scratch &sc, const void *q, uint64_t qp, ui
 
 // Preprocessed read of B rows, whose request side prep_requests enqueued on
 // stream s, into out (pitch op): the 7^L leaf products with the
-// Four-Russians kernels (one launch for all of them when their offsets are
+// Four-Russians kernels (one launch for all of them when their entries are
 // staged), then the answers from the products (masked in place when keys are
 // given). `done` is recorded by the last kernel; eb / ee take the start of
 // the first leaf's main kernel and the end of the last one's.
