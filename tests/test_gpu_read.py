@@ -261,6 +261,24 @@ def test_interest_window_across_commits(m_bits, window):
             assert np.array_equal(db.interest_vector(), want), f"epoch {e}"
 
 
+@pytest.mark.parametrize("d,z", [(1, 512), (2, 520), (1, 496)])
+def test_automatic_plan_around_the_half_wave_threshold(d, z):
+    """The automatic schedule takes half-wave 6-bucket tables above 256
+    requests over rows of 512 bytes or more (rows of 1040 bytes end in a
+    ragged 16-byte column), 5-bucket pairs at 256 or over narrower rows;
+    every answer bit-exact."""
+    n = 2000
+    D = synth.uniform_db(3100 + z, n, d * z)
+    hw = pir.PLAN_PAIRS | pir.PLAN_HALF_WAVES | pir.PLAN_PAIR_G6
+    with _db(D, d, z) as db:
+        for B in (256, 257, 700):
+            req = synth.bernoulli_requests(3200 + B + z, B, n)
+            p = db.get_plan(B)
+            want_hw = B > 256 and d * z >= 512
+            assert (p.kind == pir.KERNEL_M4R_WIDE and p.flags == hw and p.tile == 64) == want_hw, (B, d * z, p)
+            assert_rows_equal(db.read(req), oracle.pir_read(D, req, threads=8), f"auto B={B} row={d * z}")
+
+
 def test_half_wave_plan_combinations_rejected():
     """Half waves take 5- or 6-bucket paired tables only, and 6-bucket
     tables only with half waves."""
